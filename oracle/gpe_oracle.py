@@ -1,0 +1,517 @@
+"""Plain FP64 CPU oracle for the ground state of the rotating Gross-Pitaevskii energy.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the benchmark's CPU-baseline
+leg may import or run this module; the GPU library never does.  It shares no code with the GPU
+path: numpy in float64 / complex128 throughout, with numpy.fft as the transform primitive.
+
+It follows X. Antoine, A. Levitt, Q. Tang, "Efficient spectral computation of the stationary
+states of rotating Bose-Einstein condensates by the preconditioned nonlinear conjugate gradient
+method" (arXiv:1611.02045).  Citations below name the paper's sections, equations and
+algorithms.  Where the paper is silent or garbled, the reading taken is stated next to the code
+(the "reading:" notes); all of them are also listed in the design notes.
+
+Discrete conventions (Section 3):
+  * axis a spans [-L_a, L_a) periodically with M_a (even) points, h_a = 2 L_a / M_a and
+    x_k = -L_a + k h_a (reading: the phase e^{i xi_p (x_k + L)} of the paper's expansions puts the
+    first grid point at -L);
+  * frequencies xi_p = p pi / L_a for -M/2 <= p <= M/2 - 1, stored in FFT order (p = j or j - M);
+    the Nyquist mode p = -M/2 is kept in odd derivatives exactly as written (reading);
+  * forward transforms are unnormalised, the inverse carries 1/M (the paper's expansions);
+  * inner product <f, g> = h^d sum conj(f) g and unit sphere h^d sum |phi|^2 = 1 (reading: the
+    quadrature-weighted form is the one under which the paper's tabulated energies hold).
+Arrays use numpy shape (n_x,), (n_y, n_x) or (n_z, n_y, n_x): axis a lives on numpy axis -1-a.
+
+Parity status: every function here is pinned by a CPU test against closed forms, brute-force
+sums, library eigensolvers, finite differences or the paper's printed energies, except the
+exact iteration trajectory of PCG at Omega > 0, whose iteration counts the paper only shows in
+figures that are not available (parity unpinned for trajectories; final states are pinned).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+EPS64 = np.finfo(np.float64).eps
+
+
+# ----------------------------------------------------------------------------------------------
+# Grid (Section 3)
+# ----------------------------------------------------------------------------------------------
+
+def _axis_shape(dim: int, a: int, m: int) -> list:
+    s = [1] * dim
+    s[dim - 1 - a] = m
+    return s
+
+
+def coordinates(prob) -> list:
+    """Grid coordinates x_{k} = -L + k h per axis, broadcastable (Section 3, uniform grid)."""
+    out = []
+    for a in range(prob.dim):
+        M, L = prob.n[a], prob.L[a]
+        x = -L + (2.0 * L / M) * np.arange(M, dtype=np.float64)
+        out.append(x.reshape(_axis_shape(prob.dim, a, M)))
+    return out
+
+
+def frequencies(prob) -> list:
+    """Discrete Fourier frequencies xi_p = p pi / L, -M/2 <= p < M/2, in transform index order
+    (index j carries p = j for j < M/2 and p = j - M otherwise) (Section 3)."""
+    out = []
+    for a in range(prob.dim):
+        M, L = prob.n[a], prob.L[a]
+        j = np.arange(M)
+        p = np.where(j < M // 2, j, j - M).astype(np.float64)
+        out.append((p * math.pi / L).reshape(_axis_shape(prob.dim, a, M)))
+    return out
+
+
+def cell(prob) -> float:
+    """Quadrature weight h^d."""
+    return float(np.prod([2.0 * prob.L[a] / prob.n[a] for a in range(prob.dim)]))
+
+
+def inner(prob, f, g) -> complex:
+    """<f, g> = h^d sum conj(f) g (Section 3 inner product, quadrature-weighted reading)."""
+    return cell(prob) * complex(np.vdot(f.ravel(), g.ravel()))
+
+
+def norm(prob, f) -> float:
+    return math.sqrt(inner(prob, f, f).real)
+
+
+# ----------------------------------------------------------------------------------------------
+# Pseudo-spectral operators (Section 3, the matrices [[d^2_x]], [[d^2_y]], x[[d_y]], y[[d_x]])
+# ----------------------------------------------------------------------------------------------
+
+def along_axis(prob, f, a: int, symbol) -> np.ndarray:
+    """1-D transform along axis a, multiply by symbol(xi), inverse transform (the directional
+    expansions of Section 3: forward sum with e^{-i xi_p (x_k + L)}, inverse with 1/M)."""
+    ax = -1 - a
+    fh = np.fft.fft(f, axis=ax)
+    return np.fft.ifft(symbol * fh, axis=ax)
+
+
+def second_derivative(prob, f, a: int) -> np.ndarray:
+    """[[d^2_a]] f: symbol -xi^2."""
+    xi = frequencies(prob)[a]
+    return along_axis(prob, f, a, -(xi ** 2))
+
+
+def first_derivative(prob, f, a: int) -> np.ndarray:
+    """[[d_a]] f: symbol i xi (Nyquist kept as written)."""
+    xi = frequencies(prob)[a]
+    return along_axis(prob, f, a, 1j * xi)
+
+
+def laplacian(prob, f) -> np.ndarray:
+    """[[Delta]] = sum_a [[d^2_a]]."""
+    out = np.zeros_like(f, dtype=np.complex128)
+    for a in range(prob.dim):
+        out = out + second_derivative(prob, f, a)
+    return out
+
+
+def kinetic(prob, f) -> np.ndarray:
+    """T f = -(1/2) [[Delta]] f."""
+    return -0.5 * laplacian(prob, f)
+
+
+def angular_momentum(prob, f) -> np.ndarray:
+    """[[L_z]] f = -i (x [[d_y]] f - y [[d_x]] f) (Section 3; Section 2 defines
+    L_z = i (y d_x - x d_y)).  Requires dim >= 2."""
+    if prob.dim < 2:
+        raise ValueError("L_z needs at least two dimensions")
+    X = coordinates(prob)
+    return -1j * (X[0] * first_derivative(prob, f, 1) - X[1] * first_derivative(prob, f, 0))
+
+
+def linear_part(prob, V, f) -> np.ndarray:
+    """L f = (T + V - Omega L_z) f: the phi-independent part of the Hamiltonian."""
+    out = kinetic(prob, f) + V * f
+    if prob.omega != 0.0:
+        out = out - prob.omega * angular_momentum(prob, f)
+    return out
+
+
+def hamiltonian(prob, V, phi) -> np.ndarray:
+    """H_phi phi = -1/2 [[Delta]] phi + [[V]] phi + eta [[|phi|^2]] phi - Omega [[L_z]] phi
+    (Section 2 mean-field Hamiltonian, discretised in Section 3)."""
+    return linear_part(prob, V, phi) + prob.beta * np.abs(phi) ** 2 * phi
+
+
+# ----------------------------------------------------------------------------------------------
+# Energy and scalars (Section 2)
+# ----------------------------------------------------------------------------------------------
+
+@dataclass
+class EnergyParts:
+    kinetic: float
+    potential: float
+    interaction: float
+    rotation: float
+
+    @property
+    def total(self) -> float:
+        return self.kinetic + self.potential + self.interaction + self.rotation
+
+
+def energy_parts(prob, V, phi) -> EnergyParts:
+    """E(phi) = int 1/2 |grad phi|^2 + V |phi|^2 + eta/2 |phi|^4 - Omega phi^* L_z phi (Section 2),
+    with the gradient term written as <phi, T phi>."""
+    w = cell(prob)
+    kin = inner(prob, phi, kinetic(prob, phi)).real
+    rho = np.abs(phi) ** 2
+    pot = w * float(np.sum(V * rho))
+    inter = 0.5 * prob.beta * w * float(np.sum(rho * rho))
+    rot = 0.0
+    if prob.omega != 0.0:
+        rot = -prob.omega * inner(prob, phi, angular_momentum(prob, phi)).real
+    return EnergyParts(kin, pot, inter, rot)
+
+
+def energy(prob, V, phi) -> float:
+    return energy_parts(prob, V, phi).total
+
+
+def chemical_potential(prob, V, phi) -> float:
+    """lambda = <H_phi phi, phi> (Section 2, Euler-Lagrange multiplier)."""
+    return inner(prob, phi, hamiltonian(prob, V, phi)).real
+
+
+def characteristic_energy(prob, V, phi) -> float:
+    """lambda~ = int 1/2 |grad phi|^2 + V |phi|^2 + eta |phi|^4 (Section 5.5, adaptive shift;
+    no rotation term, eta rather than eta/2)."""
+    p = energy_parts(prob, V, phi)
+    return p.kinetic + p.potential + 2.0 * p.interaction
+
+
+def residual(prob, V, phi):
+    """r = H_phi phi - lambda phi with lambda = <H_phi phi, phi> (Algorithm 1)."""
+    Hphi = hamiltonian(prob, V, phi)
+    lam = inner(prob, phi, Hphi).real
+    return Hphi - lam * phi, lam
+
+
+def project(prob, phi, h) -> np.ndarray:
+    """M_phi h = h - Re<phi, h> phi: projection on the tangent space of the sphere (Section 2)."""
+    return h - inner(prob, phi, h).real * phi
+
+
+def hessian_form(prob, V, phi, f) -> float:
+    """(1/2) nabla^2 E(phi)[f, f] = <f, H_phi f> + 2 eta int (Re conj(phi) f)^2.
+    Reading: the Section 2 formula omits eta int |phi|^2 |f|^2; this is the second-order
+    coefficient of E(phi + t f) in t (pinned by finite differences)."""
+    w = cell(prob)
+    q = (np.conj(phi) * f).real
+    Hf = linear_part(prob, V, f) + prob.beta * np.abs(phi) ** 2 * f   # H_phi applied to f
+    return inner(prob, f, Hf).real + 2.0 * prob.beta * w * float(np.sum(q * q))
+
+
+# ----------------------------------------------------------------------------------------------
+# Preconditioners (Section 5.5)
+# ----------------------------------------------------------------------------------------------
+
+PRECONDITIONERS = ("none", "kinetic", "potential", "combined", "c1", "c2")
+
+
+def kinetic_preconditioner(prob, f, alpha: float) -> np.ndarray:
+    """P_Delta f = (alpha - Delta/2)^{-1} f: Fourier-diagonal with symbol 1/(alpha + |xi|^2/2)."""
+    k2 = np.zeros(prob.shape)
+    for xi in frequencies(prob):
+        k2 = k2 + xi ** 2
+    axes = tuple(range(-prob.dim, 0))
+    return np.fft.ifftn(np.fft.fftn(f, axes=axes) / (alpha + 0.5 * k2), axes=axes)
+
+
+def potential_diagonal(prob, V, phi, alpha: float) -> np.ndarray:
+    """alpha + V + eta |phi|^2, the inverse of P_V as a real diagonal (Section 5.5)."""
+    d = alpha + V + prob.beta * np.abs(phi) ** 2
+    if not np.all(d > 0.0):
+        raise ValueError("alpha + V + eta|phi|^2 must be positive for an SPD preconditioner")
+    return d
+
+
+def apply_preconditioner(prob, kind: str, V, phi, r, alpha: float | None = None) -> np.ndarray:
+    """P r for P in {I, P_Delta, P_V, P_C = P_V^{1/2} P_Delta P_V^{1/2}, P_C1 = P_V P_Delta,
+    P_C2 = P_Delta P_V}, with alpha = lambda~(phi) unless given (Section 5.5)."""
+    if alpha is None:
+        alpha = characteristic_energy(prob, V, phi)
+    if kind == "none":
+        return r.copy()
+    if kind == "kinetic":
+        return kinetic_preconditioner(prob, r, alpha)
+    d = potential_diagonal(prob, V, phi, alpha)
+    if kind == "potential":
+        return r / d
+    if kind == "combined":
+        s = 1.0 / np.sqrt(d)
+        return s * kinetic_preconditioner(prob, s * r, alpha)
+    if kind == "c1":
+        return kinetic_preconditioner(prob, r, alpha) / d
+    if kind == "c2":
+        return kinetic_preconditioner(prob, r / d, alpha)
+    raise ValueError(f"unknown preconditioner {kind!r}")
+
+
+# ----------------------------------------------------------------------------------------------
+# Line search pieces (Section 5.1)
+# ----------------------------------------------------------------------------------------------
+
+def energy_along(prob, V, phi, phat, theta: float) -> float:
+    """E(cos(theta) phi + sin(theta) phat) by the plain definition."""
+    return energy(prob, V, math.cos(theta) * phi + math.sin(theta) * phat)
+
+
+def energy_change(prob, phi, phat, Lphi, Lphat, theta: float) -> float:
+    """E(cos t phi + sin t phat) - E(phi), written without cancellation of O(1) terms.
+    Reading of the paper's acceptance test ("the energy is decreased"): both energies are
+    quadratic + quartic in the field, so the difference is expanded exactly:
+      quadratic: s^2 (<phat, L phat> - <phi, L phi>) + 2 c s Re<phi, L phat>,
+      quartic:   (eta/2) h^d sum D (2 |phi|^2 + D),  D = s^2 (|phat|^2 - |phi|^2) + 2 c s Re(conj(phi) phat),
+    which equals the plain difference up to rounding but resolves decreases far below eps*|E|."""
+    c, s = math.cos(theta), math.sin(theta)
+    w = cell(prob)
+    a = inner(prob, phi, Lphi).real
+    b = inner(prob, phi, Lphat).real
+    cc = inner(prob, phat, Lphat).real
+    quad = s * s * (cc - a) + 2.0 * c * s * b
+    rho = np.abs(phi) ** 2
+    D = s * s * (np.abs(phat) ** 2 - rho) + 2.0 * c * s * (np.conj(phi) * phat).real
+    quart = 0.5 * prob.beta * w * float(np.sum(D * (2.0 * rho + D)))
+    return quad + quart
+
+
+def theta_derivatives(prob, V, phi, phat, lam: float):
+    """E'(0) and E''(0) of theta -> E(cos theta phi + sin theta phat) for unit phat orthogonal to
+    phi.  Reading of the garbled expansion of Section 5.1: E'(0) = Re<nabla E, phat> =
+    2 Re<H_phi phi, phat>, E''(0) = nabla^2 E[phat, phat] - 2 lambda."""
+    d1 = 2.0 * inner(prob, hamiltonian(prob, V, phi), phat).real
+    d2 = 2.0 * (hessian_form(prob, V, phi, phat) - lam)
+    return d1, d2
+
+
+# ----------------------------------------------------------------------------------------------
+# PG / PCG on the sphere (Algorithms 1 and 2, Sections 5.1-5.3)
+# ----------------------------------------------------------------------------------------------
+
+@dataclass
+class SolveResult:
+    phi: np.ndarray
+    status: str
+    iters: int
+    E: float
+    lam: float
+    res_inf: float
+    restarts: int = 0
+    halvings: int = 0
+    history: list = field(default_factory=list)
+
+
+def pcg(prob, V, phi0, *, method: str = "pcg", precond: str = "combined", tol_res: float = 1e-8,
+        tol_energy: float = 0.0, max_iter: int = 10_000, theta_default: float = 0.1,
+        max_halvings: int = 30, beta_rule: str = "pr", record: bool = False) -> SolveResult:
+    """Projected preconditioned gradient (method="pg", Algorithm 1) or conjugate gradient
+    (method="pcg", Algorithm 2) minimisation of E on the unit sphere, with the step control of
+    Sections 5.1-5.2 and the residual stopping rule of Section 5.3.
+
+    Readings (the paper is silent on these):
+      * beta at n = 0 is 0; beta = max(beta^PR, 0) with numerator <r_n, P_n r_n> -
+        Re<r_{n-1}, P_n r_n> and the stored denominator <r_{n-1}, P_{n-1} r_{n-1}>;
+        beta_rule="fr" uses the Fletcher-Reeves ratio instead;
+      * p_{n-1} is used as stored (no transport between tangent spaces);
+      * not a descent direction <=> Re<r_n, p_n> >= 0, then the gradient direction is used;
+      * trial step theta_opt = -E'(0)/E''(0) when E''(0) > 0, else theta_default; clamped to
+        (0, pi/2]; halved until the energy decreases (at most max_halvings times, after which the
+        run stops with status "linesearch");
+      * phi is renormalised after every step;
+      * stop when ||r_n||_inf <= tol_res at the top of iteration n (or, when tol_energy > 0,
+        when |E_{n+1} - E_n| <= tol_energy).
+    """
+    if method not in ("pg", "pcg"):
+        raise ValueError("method must be 'pg' or 'pcg'")
+    phi = np.array(phi0, dtype=np.complex128, copy=True)
+    phi /= norm(prob, phi)
+    r_prev = p_prev = None
+    rPr_prev = 0.0
+    hist = []
+    restarts = halvings = 0
+    status = "not_converged"
+    E_prev = None
+    n = 0
+    for n in range(max_iter + 1):
+        # lambda_n, r_n
+        r, lam = residual(prob, V, phi)
+        res = float(np.max(np.abs(r)))
+        E = energy(prob, V, phi)
+        if record:
+            hist.append({"n": n, "E": E, "lam": lam, "res": res})
+        if res <= tol_res:
+            status = "converged"
+            break
+        if tol_energy > 0.0 and E_prev is not None and abs(E - E_prev) <= tol_energy:
+            status = "converged"
+            break
+        if n == max_iter:
+            break
+        E_prev = E
+        # preconditioned residual, alpha = lambda~_n (Section 5.5)
+        Pr = apply_preconditioner(prob, precond, V, phi, r)
+        rPr = inner(prob, r, Pr).real
+        # CG coefficient (Section 5.2)
+        beta = 0.0
+        if method == "pcg" and p_prev is not None and rPr_prev > 0.0:
+            if beta_rule == "fr":
+                beta = rPr / rPr_prev
+            else:
+                beta = max((rPr - inner(prob, r_prev, Pr).real) / rPr_prev, 0.0)
+        d = -Pr + beta * p_prev if beta != 0.0 else -Pr
+        p = project(prob, phi, d)
+        restarted = False
+        if inner(prob, r, p).real >= 0.0:
+            # not a descent direction: revert to the gradient step (Section 5.2)
+            p = project(prob, phi, -Pr)
+            beta = 0.0
+            restarted = True
+            restarts += 1
+        pn = norm(prob, p)
+        phat = p / pn
+        # trial step (Section 5.1): minimiser of the second-order model
+        d1, d2 = theta_derivatives(prob, V, phi, phat, lam)
+        theta = -d1 / d2 if d2 > 0.0 else theta_default
+        theta = min(max(theta, 0.0), 0.5 * math.pi)
+        Lphi = linear_part(prob, V, phi)
+        Lphat = linear_part(prob, V, phat)
+        accepted = None
+        for j in range(max_halvings + 1):
+            t = theta * 0.5 ** j
+            if t > 0.0 and energy_change(prob, phi, phat, Lphi, Lphat, t) < 0.0:
+                accepted = t
+                halvings += j
+                break
+        if accepted is None:
+            status = "linesearch"
+            break
+        if record:
+            hist[-1].update(theta=accepted, beta=beta, restarted=restarted, d1=d1, d2=d2,
+                            halvings=j)
+        new = math.cos(accepted) * phi + math.sin(accepted) * phat
+        new /= norm(prob, new)
+        r_prev, p_prev, rPr_prev = r, p, rPr
+        phi = new
+    E = energy(prob, V, phi)
+    r, lam = residual(prob, V, phi)
+    return SolveResult(phi, status, n, E, lam, float(np.max(np.abs(r))), restarts, halvings, hist)
+
+
+# ----------------------------------------------------------------------------------------------
+# Backward Euler imaginary-time scheme (Section 4), used as an independent check of PCG
+# ----------------------------------------------------------------------------------------------
+
+def conjugate_gradient(prob, apply, rhs, x0, tol: float = 1e-10, max_iter: int = 10_000):
+    """Linear CG for a Hermitian positive definite operator in the <.,.> inner product."""
+    x = x0.copy()
+    r = rhs - apply(x)
+    p = r.copy()
+    rr = inner(prob, r, r).real
+    b2 = inner(prob, rhs, rhs).real
+    it = 0
+    for it in range(max_iter):
+        if rr <= tol * tol * b2:
+            break
+        Ap = apply(p)
+        pAp = inner(prob, p, Ap).real
+        if pAp <= 0.0:
+            raise ValueError("operator is not positive definite")
+        a = rr / pAp
+        x = x + a * p
+        r = r - a * Ap
+        rr_new = inner(prob, r, r).real
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return x, it
+
+
+def backward_euler(prob, V, phi0, *, dt: float = 0.01, lambda_term: bool = True,
+                   inner_tol: float = 1e-10, tol_res: float = 1e-8, max_iter: int = 100_000,
+                   record: bool = False):
+    """BE discretisation of the normalised gradient flow (Section 4), H = H_{phi_n} frozen at the
+    current iterate (semi-implicit nonlinearity), followed by phi_{n+1} = phi~ / ||phi~||.
+    Without the lambda term: (phi~ - phi_n)/dt = -H phi~.  With it (reading): the multiplier acts
+    on the new iterate, (I/dt + H - lambda_n) phi~ = phi_n / dt.  Section 4 states that this
+    scheme equals the plain one with the effective step dt/(1 - dt lambda) and that it needs the
+    system (H - lambda) phi~ = phi_n; placing lambda_n on phi_n instead would make the term a
+    scalar factor that the normalisation removes.  The linear solve is matrix-free CG (the
+    operator is SPD for the traps used here when 1/dt > lambda_n - lambda_1)."""
+    phi = np.array(phi0, dtype=np.complex128, copy=True)
+    phi /= norm(prob, phi)
+    hist = []
+    inner_total = 0
+    status = "not_converged"
+    n = 0
+    for n in range(max_iter + 1):
+        r, lam = residual(prob, V, phi)
+        res = float(np.max(np.abs(r)))
+        if record:
+            hist.append({"n": n, "E": energy(prob, V, phi), "lam": lam, "res": res})
+        if res <= tol_res:
+            status = "converged"
+            break
+        if n == max_iter:
+            break
+        rho = np.abs(phi) ** 2
+
+        shift = lam if lambda_term else 0.0
+
+        def op(x, rho=rho, shift=shift):
+            return (1.0 / dt - shift) * x + linear_part(prob, V, x) + prob.beta * rho * x
+
+        phit, k = conjugate_gradient(prob, op, phi / dt, phi, tol=inner_tol)
+        inner_total += k
+        phi = phit / norm(prob, phit)
+    r, lam = residual(prob, V, phi)
+    out = SolveResult(phi, status, n, energy(prob, V, phi), lam, float(np.max(np.abs(r))), history=hist)
+    out.inner_iterations = inner_total
+    return out
+
+
+def backward_euler_step(prob, V, phi, dt: float, lambda_term: bool = True,
+                        inner_tol: float = 1e-13) -> np.ndarray:
+    """One BE step of Section 4 (same reading as ``backward_euler``) and normalisation."""
+    Hphi = hamiltonian(prob, V, phi)
+    shift = inner(prob, phi, Hphi).real if lambda_term else 0.0
+    rho = np.abs(phi) ** 2
+
+    def op(x):
+        return (1.0 / dt - shift) * x + linear_part(prob, V, x) + prob.beta * rho * x
+
+    phit, _ = conjugate_gradient(prob, op, phi / dt, phi, tol=inner_tol)
+    return phit / norm(prob, phit)
+
+
+def forward_euler_step(prob, V, phi, dt: float, lambda_term: bool = True) -> np.ndarray:
+    """One FE step of Section 4 followed by the normalisation step."""
+    Hphi = hamiltonian(prob, V, phi)
+    if lambda_term:
+        lam = inner(prob, phi, Hphi).real
+        new = phi - dt * (Hphi - lam * phi)
+    else:
+        new = phi - dt * Hphi
+    return new / norm(prob, new)
+
+
+# ----------------------------------------------------------------------------------------------
+# Dense assembly for tiny grids (tests)
+# ----------------------------------------------------------------------------------------------
+
+def dense_operator(prob, apply) -> np.ndarray:
+    """Matrix of a linear map on C^N, assembled column by column on the grid basis."""
+    N = int(np.prod(prob.shape))
+    A = np.zeros((N, N), dtype=np.complex128)
+    for k in range(N):
+        e = np.zeros(N, dtype=np.complex128)
+        e[k] = 1.0
+        A[:, k] = apply(e.reshape(prob.shape)).ravel()
+    return A

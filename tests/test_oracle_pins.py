@@ -1,0 +1,413 @@
+"""Pins of the FP64 CPU oracle against facts the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check uses a closed form, a brute-force
+sum written from the paper's expansions, a library eigensolver, a finite difference or a value
+printed in the paper.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import load_table
+from gpe_inputs import (Problem, gaussian, harmonic_potential, mesh, paper_initial, random_field,
+                        noisy_gaussian_1d)
+from oracle import gpe_oracle as O
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# ----------------------------------------------------------------------------------------------
+# Transforms and derivatives
+# ----------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,L", [(16, 3.0), (32, 8.0), (64, 16.0)])
+def test_derivatives_of_plane_waves_are_exact(M, L):
+    """e^{i xi_p (x + L)} is an exact eigenfunction of [[d]] (eigenvalue i xi_p) and [[d^2]]
+    (eigenvalue -xi_p^2) for every p in [-M/2, M/2 - 1], Nyquist included (kept as written)."""
+    prob = Problem(1, (M,), (L,), 0.0, 0.0)
+    (x,) = mesh(prob)
+    for p in (-M // 2, -M // 2 + 1, -3, 0, 1, 5, M // 2 - 1):
+        xi = p * math.pi / L
+        f = np.exp(1j * xi * (x + L))
+        np.testing.assert_allclose(O.first_derivative(prob, f, 0), 1j * xi * f, atol=1e-11 * max(1, abs(xi)))
+        np.testing.assert_allclose(O.second_derivative(prob, f, 0), -xi * xi * f, atol=1e-11 * max(1, xi * xi))
+
+
+def _naive_derivative(M, L, f_line, power):
+    """The paper's Section 3 formula written out as explicit sums over p = -M/2 .. M/2-1:
+    (1/M) sum_p (i xi_p)^power fhat_p e^{i xi_p (x_k + L)},  fhat_p = sum_k f_k e^{-i xi_p (x_k + L)}."""
+    h = 2.0 * L / M
+    xk = -L + h * np.arange(M)
+    out = np.zeros(M, dtype=complex)
+    for p in range(-M // 2, M // 2):
+        xi = p * math.pi / L
+        fhat = np.sum(f_line * np.exp(-1j * xi * (xk + L)))
+        out += (1j * xi) ** power * fhat * np.exp(1j * xi * (xk + L))
+    return out / M
+
+
+def test_directional_operators_match_brute_force_sums():
+    """[[d^2_x]], [[d^2_y]], x[[d_y]], y[[d_x]] and L_z on a random 2-D field against the explicit
+    sums of Section 3 (distinct sizes and half-widths per axis to catch transposed axes)."""
+    prob = Problem(2, (8, 6), (3.0, 2.0), 0.0, 0.0)
+    f = random_field(prob, 7)
+    x, y = mesh(prob)
+    nx, ny = prob.n
+    dxx = np.zeros_like(f)
+    dx = np.zeros_like(f)
+    for j in range(ny):
+        dxx[j, :] = _naive_derivative(nx, prob.L[0], f[j, :], 2)
+        dx[j, :] = _naive_derivative(nx, prob.L[0], f[j, :], 1)
+    dyy = np.zeros_like(f)
+    dy = np.zeros_like(f)
+    for i in range(nx):
+        dyy[:, i] = _naive_derivative(ny, prob.L[1], f[:, i], 2)
+        dy[:, i] = _naive_derivative(ny, prob.L[1], f[:, i], 1)
+    np.testing.assert_allclose(O.second_derivative(prob, f, 0), dxx, atol=1e-12)
+    np.testing.assert_allclose(O.second_derivative(prob, f, 1), dyy, atol=1e-12)
+    np.testing.assert_allclose(O.laplacian(prob, f), dxx + dyy, atol=1e-12)
+    lz = -1j * (x * dy - y * dx)
+    np.testing.assert_allclose(O.angular_momentum(prob, f), lz, atol=1e-12)
+
+
+def test_angular_momentum_eigenfunctions():
+    """L_z (x + i y) g(r) = +(x + i y) g(r), L_z (x - i y) g = -(x - i y) g, L_z g(r) = 0
+    for a radial Gaussian g (sign convention L_z = -i (x d_y - y d_x))."""
+    prob = Problem(2, (64, 64), (8.0, 8.0), 0.0, 0.0)
+    x, y = mesh(prob)
+    g = np.exp(-0.5 * (x ** 2 + y ** 2)) + 0j
+    np.testing.assert_allclose(O.angular_momentum(prob, (x + 1j * y) * g), (x + 1j * y) * g, atol=1e-11)
+    np.testing.assert_allclose(O.angular_momentum(prob, (x - 1j * y) * g), -(x - 1j * y) * g, atol=1e-11)
+    np.testing.assert_allclose(O.angular_momentum(prob, g), 0 * g, atol=1e-11)
+
+
+def test_operators_are_hermitian():
+    """T, L_z and the frozen H_phi are Hermitian in the weighted inner product (Section 3)."""
+    prob = Problem(2, (8, 8), (4.0, 4.0), 30.0, 0.7)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 3)
+    rho = np.abs(phi) ** 2
+    H = O.dense_operator(prob, lambda f: O.linear_part(prob, V, f) + prob.beta * rho * f)
+    Lz = O.dense_operator(prob, lambda f: O.angular_momentum(prob, f))
+    for A in (H, Lz):
+        np.testing.assert_allclose(A, A.conj().T, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------------------------
+# Energy, chemical potential, derivatives
+# ----------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,L,gam,E_exact", [
+    (1, (256,), (16.0,), (1.0,), 0.5),
+    (2, (64, 64), (8.0, 8.0), (1.0, 1.0), 1.0),
+    (3, (64, 64, 64), (8.0, 8.0, 6.0), (1.0, 1.0, 2.0), 2.0),
+])
+def test_gaussian_is_exact_ground_state_at_beta0(dim, n, L, gam, E_exact):
+    """beta = 0, V = sum gamma^2 x^2 / 2: the Gaussian exp(-sum gamma x^2/2) is the ground state
+    with E = lambda = sum gamma / 2 (any |Omega| < 1 in 2-D/3-D); spectral accuracy makes this
+    hold to rounding on these boxes."""
+    for omega in ((0.0,) if dim == 1 else (0.0, 0.6)):
+        prob = Problem(dim, n, L, 0.0, omega)
+        V = harmonic_potential(prob, gam + (1.0,) * (3 - dim))
+        g = gaussian(prob, gam + (1.0,) * (3 - dim))
+        assert abs(O.energy(prob, V, g) - E_exact) < 1e-12
+        r, lam = O.residual(prob, V, g)
+        assert abs(lam - E_exact) < 1e-12
+        assert np.max(np.abs(r)) < 1e-11
+
+
+def test_scalar_identities():
+    """lambda - E = (eta/2) h^d sum |phi|^4 and lambda~ - lambda = Omega Re<phi, L_z phi>."""
+    prob = Problem(2, (32, 32), (6.0, 6.0), 123.0, 0.55)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 11, envelope=0.2)
+    w = O.cell(prob)
+    lam = O.chemical_potential(prob, V, phi)
+    E = O.energy(prob, V, phi)
+    assert abs((lam - E) - 0.5 * prob.beta * w * np.sum(np.abs(phi) ** 4)) < 1e-10 * abs(lam)
+    lt = O.characteristic_energy(prob, V, phi)
+    lz = O.inner(prob, phi, O.angular_momentum(prob, phi)).real
+    assert abs((lt - lam) - prob.omega * lz) < 1e-10 * abs(lam)
+
+
+def test_gradient_matches_energy_finite_difference():
+    """E(phi + t f) - E(phi - t f) = 2 t * 2 Re<H_phi phi, f> + O(t^3): nabla E = 2 H_phi phi."""
+    prob = Problem(2, (32, 32), (6.0, 6.0), 200.0, 0.7)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 1, envelope=0.1)
+    f = random_field(prob, 2, envelope=0.1)
+    t = 1e-5
+    fd = (O.energy(prob, V, phi + t * f) - O.energy(prob, V, phi - t * f)) / (2 * t)
+    an = 2.0 * O.inner(prob, O.hamiltonian(prob, V, phi), f).real
+    assert abs(fd - an) < 1e-7 * abs(an)
+
+
+def test_hessian_form_matches_second_difference():
+    """E(phi + t f) - 2 E(phi) + E(phi - t f) = t^2 nabla^2 E[f, f] + O(t^4); this fixes the
+    missing eta int |phi|^2 |f|^2 term of the printed second-derivative formula."""
+    prob = Problem(2, (32, 32), (6.0, 6.0), 300.0, 0.4)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 4, envelope=0.1)
+    f = random_field(prob, 5, envelope=0.1)
+    t = 1e-3
+    fd = (O.energy(prob, V, phi + t * f) - 2 * O.energy(prob, V, phi) + O.energy(prob, V, phi - t * f)) / t ** 2
+    an = 2.0 * O.hessian_form(prob, V, phi, f)
+    assert abs(fd - an) < 1e-5 * abs(an)
+    # the printed form (without eta int |phi|^2 |f|^2) is measurably different
+    w = O.cell(prob)
+    missing = 2.0 * prob.beta * w * np.sum(np.abs(phi) ** 2 * np.abs(f) ** 2)
+    assert abs(missing) > 1e3 * abs(fd - an)
+
+
+def test_theta_derivatives_match_finite_differences():
+    """E'(0), E''(0) of theta -> E(cos theta phi + sin theta phat) against central differences."""
+    prob = Problem(2, (32, 32), (6.0, 6.0), 150.0, 0.6)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 8, envelope=0.15)
+    q = O.project(prob, phi, random_field(prob, 9, envelope=0.15))
+    phat = q / O.norm(prob, q)
+    lam = O.chemical_potential(prob, V, phi)
+    d1, d2 = O.theta_derivatives(prob, V, phi, phat, lam)
+    t = 1e-4
+    Ep, E0, Em = (O.energy_along(prob, V, phi, phat, s) for s in (t, 0.0, -t))
+    assert abs((Ep - Em) / (2 * t) - d1) < 1e-7 * abs(d1)
+    assert abs((Ep - 2 * E0 + Em) / t ** 2 - d2) < 1e-5 * abs(d2)
+
+
+def test_energy_change_equals_plain_difference():
+    prob = Problem(2, (32, 32), (6.0, 6.0), 400.0, 0.8)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 12, envelope=0.15)
+    q = O.project(prob, phi, random_field(prob, 13, envelope=0.15))
+    phat = q / O.norm(prob, q)
+    Lphi, Lphat = O.linear_part(prob, V, phi), O.linear_part(prob, V, phat)
+    for t in (1e-3, 0.05, 0.4, 1.2):
+        plain = O.energy_along(prob, V, phi, phat, t) - O.energy(prob, V, phi)
+        assert abs(O.energy_change(prob, phi, phat, Lphi, Lphat, t) - plain) < 1e-10 * (1 + abs(plain))
+
+
+# ----------------------------------------------------------------------------------------------
+# Preconditioners
+# ----------------------------------------------------------------------------------------------
+
+def test_kinetic_preconditioner_on_plane_wave():
+    """P_Delta e^{i (xi x + mu y)} = e^{...} / (alpha + (xi^2 + mu^2)/2)."""
+    prob = Problem(2, (16, 8), (4.0, 3.0), 0.0, 0.0)
+    x, y = mesh(prob)
+    xi, mu = 3 * math.pi / 4.0, -2 * math.pi / 3.0
+    f = np.exp(1j * (xi * (x + 4.0) + mu * (y + 3.0)))
+    alpha = 1.7
+    np.testing.assert_allclose(O.kinetic_preconditioner(prob, f, alpha), f / (alpha + 0.5 * (xi ** 2 + mu ** 2)), atol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["kinetic", "potential", "combined"])
+def test_symmetric_preconditioners_are_spd(kind):
+    prob = Problem(2, (8, 8), (4.0, 4.0), 50.0, 0.3)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 21)
+    P = O.dense_operator(prob, lambda r: O.apply_preconditioner(prob, kind, V, phi, r))
+    np.testing.assert_allclose(P, P.conj().T, atol=1e-13)
+    assert np.min(np.linalg.eigvalsh(0.5 * (P + P.conj().T))) > 0.0
+
+
+def test_combined_preconditioner_composition():
+    """P_C = P_V^{1/2} P_Delta P_V^{1/2}; P_C1 = P_V P_Delta; P_C2 = P_Delta P_V, as matrices."""
+    prob = Problem(2, (8, 8), (4.0, 4.0), 50.0, 0.3)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 22)
+    a = O.characteristic_energy(prob, V, phi)
+    Pd = O.dense_operator(prob, lambda r: O.apply_preconditioner(prob, "kinetic", V, phi, r))
+    Pv = O.dense_operator(prob, lambda r: O.apply_preconditioner(prob, "potential", V, phi, r))
+    s = np.diag(np.sqrt(np.real(np.diag(Pv))))
+    for kind, ref in (("combined", s @ Pd @ s), ("c1", Pv @ Pd), ("c2", Pd @ Pv)):
+        P = O.dense_operator(prob, lambda r: O.apply_preconditioner(prob, kind, V, phi, r))
+        np.testing.assert_allclose(P, ref, atol=1e-13)
+    assert a > 0
+
+
+def test_preconditioner_rejects_non_positive_shift():
+    prob = Problem(1, (16,), (4.0,), 1.0, 0.0)
+    V = -harmonic_potential(prob) - 100.0
+    phi = random_field(prob, 1)
+    with pytest.raises(ValueError):
+        O.apply_preconditioner(prob, "potential", V, phi, phi, alpha=1.0)
+
+
+# ----------------------------------------------------------------------------------------------
+# Gradient-flow schemes (Section 4) and the PG/FE equivalence (Section 5.1)
+# ----------------------------------------------------------------------------------------------
+
+def test_effective_time_step_of_lambda_schemes():
+    """For a linear problem (beta = 0), one FE step with the lambda term equals one plain FE step
+    with dt/(1 + dt lambda), and one BE step with the lambda term equals one plain BE step with
+    dt/(1 - dt lambda) (Section 4)."""
+    prob = Problem(2, (16, 16), (5.0, 5.0), 0.0, 0.3)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 31, envelope=0.2)
+    lam = O.chemical_potential(prob, V, phi)
+    dt = 0.05
+    fe = O.forward_euler_step(prob, V, phi, dt, True)
+    fe0 = O.forward_euler_step(prob, V, phi, dt / (1 + dt * lam), False)
+    np.testing.assert_allclose(fe, fe0, atol=1e-12)
+    be = O.backward_euler_step(prob, V, phi, dt, True)
+    be0 = O.backward_euler_step(prob, V, phi, dt / (1 - dt * lam), False)
+    np.testing.assert_allclose(be, be0, atol=1e-10)
+
+
+def test_backward_euler_contraction_rate():
+    """Plain BE on a linear problem is a shift-and-invert power iteration: the error on the
+    second eigenvector contracts by (1 + dt lambda_1)/(1 + dt lambda_2) per step (Section 4)."""
+    prob = Problem(1, (32,), (6.0,), 0.0, 0.0)
+    V = harmonic_potential(prob)
+    H = O.dense_operator(prob, lambda f: O.linear_part(prob, V, f))
+    w, U = np.linalg.eigh(0.5 * (H + H.conj().T))
+    dt = 0.3
+    # start on the first two even/odd modes
+    phi = (U[:, 0] + 0.5 * U[:, 1]).reshape(prob.shape)
+    ratios = []
+    c_prev = None
+    for _ in range(6):
+        phi = O.backward_euler_step(prob, V, phi, dt, lambda_term=False)
+        v = phi.ravel()
+        c = abs(np.vdot(U[:, 1], v)) / abs(np.vdot(U[:, 0], v))
+        if c_prev is not None:
+            ratios.append(c / c_prev)
+        c_prev = c
+    expect = (1 + dt * w[0]) / (1 + dt * w[1])
+    np.testing.assert_allclose(ratios, expect, rtol=1e-8)
+
+
+def test_forward_euler_cfl_bound():
+    """FE diverges from the ground state when dt > 2/lambda_N and contracts below it."""
+    prob = Problem(1, (32,), (6.0,), 0.0, 0.0)
+    V = harmonic_potential(prob)
+    H = O.dense_operator(prob, lambda f: O.linear_part(prob, V, f))
+    lmax = np.max(np.linalg.eigvalsh(0.5 * (H + H.conj().T)))
+    g = gaussian(prob)
+    for dt, stable in ((1.9 / lmax, True), (2.2 / lmax, False)):
+        phi = g + 1e-6 * random_field(prob, 5)
+        phi = phi / O.norm(prob, phi)
+        for _ in range(400):
+            phi = O.forward_euler_step(prob, V, phi, dt, lambda_term=False)
+        dist = min(O.norm(prob, phi - g), O.norm(prob, phi + g))
+        assert (dist < 1e-3) == stable
+
+
+def test_pg_step_equals_normalised_fe_lambda_step():
+    """With P = I, the PG step of angle theta equals the normalised FE-lambda step with
+    alpha = tan(theta)/||r|| (Section 5.1, one-to-one theta <-> alpha map)."""
+    prob = Problem(2, (16, 16), (5.0, 5.0), 80.0, 0.5)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, 41, envelope=0.2)
+    r, lam = O.residual(prob, V, phi)
+    p = O.project(prob, phi, -r)
+    np.testing.assert_allclose(p, -r, atol=1e-12)
+    pn = O.norm(prob, p)
+    theta = 0.3
+    pg = math.cos(theta) * phi + math.sin(theta) * p / pn
+    alpha = math.tan(theta) / O.norm(prob, r)
+    fe = phi - alpha * r
+    fe = fe / O.norm(prob, fe)
+    np.testing.assert_allclose(pg, fe, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------------------------
+# Solvers
+# ----------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method,precond", [("pcg", "combined"), ("pg", "combined"), ("pcg", "kinetic"),
+                                            ("pcg", "potential"), ("pcg", "none")])
+def test_energy_decreases_and_norm_is_kept(method, precond):
+    prob = Problem(2, (32, 32), (8.0, 8.0), 100.0, 0.5)
+    V = harmonic_potential(prob)
+    phi0 = paper_initial(prob, "d", 0.5)
+    res = O.pcg(prob, V, phi0, method=method, precond=precond, tol_res=1e-30, max_iter=40, record=True)
+    E = [h["E"] for h in res.history]
+    assert all(E[k + 1] < E[k] + 1e-13 * abs(E[k]) for k in range(len(E) - 1))
+    assert abs(O.norm(prob, res.phi) - 1.0) < 1e-14
+
+
+def test_pcg_linear_case_matches_dense_eigensolver():
+    """beta = 0: the minimum of E on the sphere is the lowest eigenvalue of the discrete
+    Hamiltonian (any Omega); PCG must reach it (numpy.linalg.eigh on the assembled matrix)."""
+    prob = Problem(2, (16, 16), (5.0, 5.0), 0.0, 0.6)
+    V = harmonic_potential(prob)
+    H = O.dense_operator(prob, lambda f: O.linear_part(prob, V, f))
+    l1 = np.linalg.eigvalsh(0.5 * (H + H.conj().T))[0]
+    res = O.pcg(prob, V, random_field(prob, 51, envelope=0.1), tol_res=1e-11, max_iter=2000)
+    assert res.status == "converged"
+    assert abs(res.E - l1) < 1e-11 and abs(res.lam - l1) < 1e-11
+
+
+def test_pcg_1d_beta0_gives_half():
+    """1-D harmonic trap at beta = 0 from the seeded noisy Gaussian: E = 1/2."""
+    prob = Problem(1, (256,), (16.0,), 0.0, 0.0)
+    V = harmonic_potential(prob)
+    res = O.pcg(prob, V, noisy_gaussian_1d(prob), tol_res=1e-10, max_iter=500)
+    assert res.status == "converged"
+    assert abs(res.E - 0.5) < 1e-12
+
+
+def test_omega0_ground_state_is_lowest_eigenvector_of_frozen_hamiltonian():
+    """At Omega = 0 the positive ground state satisfies lambda = lambda_1(H_{phi*})."""
+    prob = Problem(2, (16, 16), (6.0, 6.0), 60.0, 0.0)
+    V = harmonic_potential(prob)
+    res = O.pcg(prob, V, gaussian(prob), tol_res=1e-11, max_iter=2000)
+    rho = np.abs(res.phi) ** 2
+    H = O.dense_operator(prob, lambda f: O.linear_part(prob, V, f) + prob.beta * rho * f)
+    l1 = np.linalg.eigvalsh(0.5 * (H + H.conj().T))[0]
+    assert abs(res.lam - l1) < 1e-10
+
+
+@pytest.mark.parametrize("lambda_term", [True, False])
+def test_backward_euler_and_pcg_agree(lambda_term):
+    """Two independent algorithms (BE imaginary time with CG inner solves, PCG on the sphere)
+    reach the same ground state on a problem with a unique positive minimiser (Omega = 0)."""
+    prob = Problem(2, (32, 32), (8.0, 8.0), 100.0, 0.0)
+    V = harmonic_potential(prob)
+    phi0 = gaussian(prob)
+    pc = O.pcg(prob, V, phi0, tol_res=1e-10, max_iter=2000)
+    be = O.backward_euler(prob, V, phi0, dt=0.05, lambda_term=lambda_term, tol_res=1e-9, inner_tol=1e-12,
+                          max_iter=3000)
+    assert pc.status == "converged" and be.status == "converged"
+    assert abs(pc.E - be.E) < 1e-10 * abs(pc.E)
+    np.testing.assert_allclose(np.abs(pc.phi) ** 2, np.abs(be.phi) ** 2, atol=1e-9)
+
+
+# ----------------------------------------------------------------------------------------------
+# The paper's printed energies
+# ----------------------------------------------------------------------------------------------
+
+COLS = ["a", "b", "b2", "c", "c2", "d", "d2", "e", "e2", "f"]
+
+
+@pytest.mark.parametrize("kind", ["a", "b", "b2"])
+def test_sector_energies_from_paper_table(kind):
+    """Fixed-grid table: start (a) gives 8.5118 for every Omega, start (b) 8.7606 - Omega and its
+    conjugate 8.7606 + Omega (the states stay in the m = 0 and m = +-1 sectors).  Run on the
+    paper's 2-D grid spacing h = 1/16 would take 512^2; 256^2 (h = 1/8) already agrees to the
+    printed 4 decimals."""
+    table = {row[0]: dict(zip(COLS, row[1:])) for row in load_table("paper_energies_fixed_grid.txt")}
+    omega = 0.5
+    prob = Problem(2, (256, 256), (16.0, 16.0), 500.0, omega)
+    V = harmonic_potential(prob)
+    res = O.pcg(prob, V, paper_initial(prob, kind, omega), tol_res=1e-7, max_iter=500)
+    assert res.status == "converged"
+    assert abs(res.E - table[omega][kind]) < 6e-5
+
+
+@pytest.mark.slow
+def test_vortex_lattice_lands_on_tabulated_minimum():
+    """Start (d) at Omega = 0.5 must converge to one of the local minima the paper tabulates at
+    that Omega (fixed-grid or multigrid table), to the printed 4 decimals."""
+    fixed = {row[0]: row[1:] for row in load_table("paper_energies_fixed_grid.txt")}
+    multi = {row[0]: row[1:] for row in load_table("paper_energies_multigrid.txt")}
+    omega = 0.5
+    known = set(fixed[omega]) | set(multi[omega])
+    prob = Problem(2, (256, 256), (16.0, 16.0), 500.0, omega)
+    V = harmonic_potential(prob)
+    res = O.pcg(prob, V, paper_initial(prob, "d", omega), tol_res=1e-6, max_iter=3000)
+    assert res.status == "converged"
+    assert min(abs(res.E - e) for e in known) < 6e-5
+    assert res.E >= min(known) - 1e-4
