@@ -1,0 +1,181 @@
+/*
+ * gpe.h -- C ABI of libgpe, the gfx950 implementation of the hot path of the preconditioned
+ * nonlinear conjugate-gradient (PCG) ground-state solver for the rotating Gross-Pitaevskii
+ * energy of Antoine, Levitt and Tang (arXiv:1611.02045).
+ *
+ * Problem (Section 2): minimise
+ *     E(phi) = int 1/2 |grad phi|^2 + V |phi|^2 + beta/2 |phi|^4 - omega conj(phi) L_z phi
+ * over ||phi|| = 1, where L_z = -i (x d_y - y d_x) and beta is the paper's nonlinearity eta.
+ * Discretisation (Section 3): periodic box prod_a [-L_a, L_a) with n_a points per axis,
+ * h_a = 2 L_a / n_a, x_k = -L_a + k h_a; Fourier pseudo-spectral derivatives with frequencies
+ * xi_p = p pi / L_a, -n_a/2 <= p < n_a/2 (the Nyquist mode is kept in odd derivatives).
+ * Inner products are quadrature weighted: <f, g> = h^d sum conj(f) g, and ||phi||^2 = h^d sum |phi|^2.
+ *
+ * Data layout: every field is a C-ordered array with x fastest, i.e. element (k_z, k_y, k_x) at
+ * offset (k_z * n_y + k_y) * n_x + k_x.  Wave functions are interleaved complex (re, im) of the
+ * plan's real type; potentials are real of the same type.  All field pointers are DEVICE
+ * pointers owned by the caller; the library never frees them and does not keep them after the
+ * call's work has completed on the stream.  Host pointers are marked "host".
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls that
+ * return host scalars synchronise that stream; the others are asynchronous.  A plan owns device
+ * workspace and must not be used from two streams or threads at once.
+ *
+ * Errors: every entry point returns a gpe_status_t; negative values are errors, and
+ * gpe_last_error() returns a thread-local message describing the last error.  No C++ exception
+ * crosses this boundary.
+ *
+ * Supported grids: dim in {1, 2, 3}; every n_a a power of two with 8 <= n_a <= 1024.
+ */
+#ifndef GPE_H
+#define GPE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Problem description (Sections 2-3).  n[a] and L[a] for a >= dim are ignored. */
+typedef struct gpe_problem {
+    int32_t dim;    /* 1, 2 or 3 */
+    int32_t n[3];   /* points per axis (x, y, z) */
+    double  L[3];   /* half-widths: axis a spans [-L[a], L[a]) */
+    double  beta;   /* nonlinearity strength (the paper's eta) */
+    double  omega;  /* rotation speed; must be 0 when dim == 1 */
+} gpe_problem_t;
+
+/* Storage and arithmetic type of the caller's fields. */
+typedef enum { GPE_F64 = 0, GPE_F32 = 1 } gpe_dtype_t;
+
+/* Preconditioners of Section 5.5: identity, P_Delta = (alpha - Delta/2)^{-1},
+ * P_V = (alpha + V + beta|phi|^2)^{-1}, the symmetric P_C = P_V^{1/2} P_Delta P_V^{1/2},
+ * and the non-symmetric P_C1 = P_V P_Delta, P_C2 = P_Delta P_V. */
+typedef enum {
+    GPE_P_NONE = 0, GPE_P_KINETIC = 1, GPE_P_POTENTIAL = 2, GPE_P_COMBINED = 3,
+    GPE_P_C1 = 4, GPE_P_C2 = 5
+} gpe_precond_t;
+
+typedef enum {
+    GPE_OK = 0,             /* success / converged */
+    GPE_NOT_CONVERGED = 1,  /* max_iter reached; results are still written */
+    GPE_EINVAL = -1,        /* invalid argument, non-SPD preconditioner, NULL pointer */
+    GPE_EUNSUPPORTED = -2,  /* valid but unsupported (grid size, dimension) */
+    GPE_EHIP = -3,          /* HIP runtime error */
+    GPE_ENONFINITE = -4,    /* NaN or Inf met in the input or during the iteration */
+    GPE_ELINESEARCH = -5    /* no step decreased the energy (FP64 phase) */
+} gpe_status_t;
+
+typedef struct gpe_plan gpe_plan_t;
+
+/* Create a plan: validates the problem, builds twiddle tables and allocates workspace on the
+ * current device.  On success *out receives the plan; on error *out is set to NULL. */
+int gpe_plan_create(const gpe_problem_t* prob, int dtype, gpe_plan_t** out);
+int gpe_plan_destroy(gpe_plan_t* plan);
+
+/* Energy E(phi) of Section 2 in its discrete form (Section 3), reduced in FP64.
+ * phi: device, complex, one field.  V: device, real.  E: host, receives the total.
+ * parts: host, nullable; receives {kinetic <phi,T phi>, potential <phi,V phi>,
+ * interaction beta/2 h^d sum|phi|^4, rotation -omega Re<phi,L_z phi>}.  Synchronises. */
+int gpe_energy(gpe_plan_t* plan, const void* phi, const void* V, double* E, double* parts,
+               void* stream);
+
+/* Hphi = H_phi phi = -1/2 Delta phi + V phi + beta |phi|^2 phi - omega L_z phi (Section 2
+ * mean-field Hamiltonian, Section 3 discretisation).  Device pointers; Hphi must not alias phi.
+ * Asynchronous. */
+int gpe_apply_H(gpe_plan_t* plan, const void* phi, const void* V, void* Hphi, void* stream);
+
+/* Batched form: `count` wave functions stored back to back (field b at phi + b * N), all with
+ * the plan's problem and the same potential V.  Asynchronous. */
+int gpe_apply_H_batched(gpe_plan_t* plan, int count, const void* phi, const void* V, void* Hphi,
+                        void* stream);
+
+/* Pr = P r for the preconditioner `kind` of Section 5.5 at the point phi, with shift alpha.
+ * alpha = NaN selects the adaptive shift lambda~(phi) = <phi,T phi> + <phi,V phi> +
+ * beta h^d sum|phi|^4 (Section 5.5), computed on the device.  Returns GPE_EINVAL when
+ * alpha + V + beta|phi|^2 is not positive everywhere (P would not be SPD); that check
+ * synchronises the stream.  Pr must not alias r or phi. */
+int gpe_precond(gpe_plan_t* plan, int kind, const void* phi, const void* V, double alpha,
+                const void* r, void* Pr, void* stream);
+
+/* Solver options. */
+typedef struct gpe_pcg_opts {
+    int32_t method;        /* 0 = projected preconditioned gradient (Algorithm 1), 1 = PCG (Algorithm 2) */
+    int32_t precond;       /* gpe_precond_t */
+    double  tol_res_inf;   /* stop when ||H_phi phi - lambda phi||_inf <= tol (Section 5.3) */
+    double  tol_energy;    /* if > 0, also stop when |E_{n+1} - E_n| <= tol_energy */
+    int64_t max_iter;
+    int32_t precision;     /* 0 = FP64 throughout; 1 = mixed: FP32 fields until the switch, then FP64 */
+    int32_t beta_rule;     /* 0 = Polak-Ribiere max(beta_PR, 0); 1 = Fletcher-Reeves */
+    double  switch_res;    /* mixed: leave FP32 once ||r||_inf <= switch_res (or on stagnation) */
+    double  theta_default; /* trial angle when the quadratic model has no minimum */
+    int32_t max_halvings;  /* step halvings before the line search gives up */
+    int32_t refresh_every; /* recompute L phi from phi every this many iterations (0 = never) */
+    int32_t check_every;   /* iterations queued between convergence polls */
+    int32_t record_history;/* nonzero: keep per-iteration scalars (see gpe_pcg_history) */
+} gpe_pcg_opts_t;
+
+typedef struct gpe_pcg_report {
+    int32_t status;        /* gpe_status_t of this solve */
+    int32_t switched;      /* mixed mode: 1 if the FP64 phase was entered */
+    int64_t iters;         /* total iterations (both phases) */
+    int64_t iters_fp32;    /* iterations done in FP32 */
+    int64_t restarts;      /* non-descent restarts (Section 5.2) */
+    int64_t halvings;      /* total step halvings */
+    double  E, lambda, res_inf;   /* final energy, chemical potential, ||r||_inf (fresh FP64) */
+    double  dE;            /* |E_n - E_{n-1}| of the last step */
+    double  dphi_inf;      /* ||phi_n - phi_{n-1}||_inf of the last step */
+    double  seconds;       /* wall time of the solve (excluding plan creation) */
+} gpe_pcg_report_t;
+
+/* Fill *opts with defaults: PCG, P_C, tol 1e-8, 20000 iterations, FP64, Polak-Ribiere,
+ * switch_res 1e-6, theta_default 0.1, 30 halvings, refresh every 50, poll every 16. */
+void gpe_pcg_opts_default(gpe_pcg_opts_t* opts);
+
+/* Ground state by PG / PCG on the unit sphere (Algorithms 1-2 with the step control of
+ * Sections 5.1-5.2).  phi_inout: device, the initial guess (normalised on entry by the solver),
+ * overwritten by the final iterate.  V: device.  report: host.  Synchronises.
+ * Returns GPE_OK when converged, GPE_NOT_CONVERGED at max_iter, or an error. */
+int gpe_pcg_solve(gpe_plan_t* plan, const void* V, void* phi_inout, const gpe_pcg_opts_t* opts,
+                  gpe_pcg_report_t* report, void* stream);
+
+/* Per-iteration record of the last solve when opts->record_history was set.  hist: host,
+ * receives up to `cap` rows of 8 doubles {n, E_n, lambda_n, ||r_n||_inf, theta_n, beta_n,
+ * halvings_n, restarted_n}; returns the number of rows written (>= 0) or an error. */
+int gpe_pcg_history(gpe_plan_t* plan, double* hist, int cap);
+
+/* Independent solves of `count` problems (possibly different grids, beta, omega, L) in one
+ * iteration loop; instances of equal grid share each kernel launch and converged instances
+ * are masked out.  V[i], phi_inout[i]: device fields of instance i in its own layout and in
+ * the type `dtype`.  reports: host array of `count`.  Returns the worst status.  Synchronises. */
+int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void* const* V,
+                          void* const* phi_inout, const gpe_pcg_opts_t* opts,
+                          gpe_pcg_report_t* reports, void* stream);
+
+/* Backward of the energy (conjugate-Wirtinger convention of real-valued losses):
+ * grad_phi = 2 h^d H_phi phi (device, complex), grad_V = h^d |phi|^2 (device, real, nullable),
+ * *dE_dbeta = 1/2 h^d sum |phi|^4 and *dE_domega = -Re<phi, L_z phi> (host, nullable).
+ * Synchronises when a host scalar is requested. */
+int gpe_energy_grad(gpe_plan_t* plan, const void* phi, const void* V, void* grad_phi, void* grad_V,
+                    double* dE_dbeta, double* dE_domega, void* stream);
+
+/* Implicit adjoint at a converged ground state phi_star: solves A mu = M rhs on the tangent
+ * space {f : Re<phi_star, f> = Re<i phi_star, f> = 0} with A = Pi (1/2 nabla^2 E - lambda) Pi,
+ * where 1/2 nabla^2 E [f] = H f + 2 beta Re(conj(phi) f) phi (the second derivative of
+ * Section 2 with its interaction term completed), by preconditioned linear CG (P_C).
+ * rhs, mu: device complex fields; opts->tol_res_inf is the relative residual tolerance and
+ * opts->max_iter the iteration cap.  report: host, nullable.  Synchronises. */
+int gpe_adjoint_solve(gpe_plan_t* plan, const void* phi_star, const void* V, const void* rhs,
+                      void* mu, const gpe_pcg_opts_t* opts, gpe_pcg_report_t* report, void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* gpe_last_error(void);
+
+/* Library version string. */
+const char* gpe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPE_H */

@@ -1,0 +1,163 @@
+// Shared device/host definitions of libgpe: complex arithmetic, grid geometry, per-instance
+// solver scalars and the deterministic block reduction used by every reducing kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpe {
+
+// ------------------------------------------------------------------------------------------------
+// Complex numbers stored interleaved (re, im); alignment gives 8/16-byte vector loads.
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) C2 {
+    T x, y;
+};
+
+template <typename T> __host__ __device__ __forceinline__ C2<T> mk(T a, T b) { C2<T> r; r.x = a; r.y = b; return r; }
+template <typename T> __host__ __device__ __forceinline__ C2<T> add(C2<T> a, C2<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T> __host__ __device__ __forceinline__ C2<T> sub(C2<T> a, C2<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T> __host__ __device__ __forceinline__ C2<T> scl(C2<T> a, T s) { return mk(a.x * s, a.y * s); }
+template <typename T> __host__ __device__ __forceinline__ C2<T> mul(C2<T> a, C2<T> b) {
+    return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T> __host__ __device__ __forceinline__ C2<T> mulc(C2<T> a, C2<T> b) {
+    return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T> __host__ __device__ __forceinline__ T abs2(C2<T> a) { return a.x * a.x + a.y * a.y; }
+// Re(conj(a) b)
+template <typename T> __host__ __device__ __forceinline__ T redot(C2<T> a, C2<T> b) { return a.x * b.x + a.y * b.y; }
+// a * (i s): multiplication by a purely imaginary number
+template <typename T> __host__ __device__ __forceinline__ C2<T> muli(C2<T> a, T s) { return mk(-a.y * s, a.x * s); }
+
+// ------------------------------------------------------------------------------------------------
+// Grid geometry of one problem (Section 3).
+// ------------------------------------------------------------------------------------------------
+struct Geo {
+    int dim;
+    int n[3];       // points per axis (1 for unused axes)
+    int lg[3];      // log2 n
+    double L[3];    // half-widths
+    double h[3];    // spacings 2L/n
+    double cell;    // h^d
+    int64_t N;      // points per field
+};
+
+// Frequency xi of transform index j on an axis of n points and half-width L (Nyquist kept).
+__device__ __forceinline__ double freq_of(int j, int n, double L) {
+    int p = (j < (n >> 1)) ? j : j - n;
+    return (double)p * (3.141592653589793238462643383279502884 / L);
+}
+// Grid coordinate x_k = -L + k h.
+__device__ __forceinline__ double coord_of(int k, double L, double h) { return -L + (double)k * h; }
+
+// ------------------------------------------------------------------------------------------------
+// Per-instance solver state (FP64).  One struct per instance, resident in device memory.
+// ------------------------------------------------------------------------------------------------
+struct Scal {
+    // problem parameters (per instance: batched solves mix boxes, beta and omega)
+    double beta, omega, cell;
+    double L[3], h[3];
+    // scalars of the current iterate phi_n
+    double a;          // <phi, L phi>, L = T + V - omega L_z (tracked field)
+    double aR;         // <phi, R phi>, R = -omega L_z
+    double q4;         // h^d sum |phi|^4
+    double nrm2;       // ||phi||^2
+    double lam;        // lambda_n
+    double lamt;       // lambda~_n (preconditioner shift)
+    double E;          // E(phi_n)
+    double E_prev;     // E(phi_{n-1})
+    double res;        // ||r_n||_inf
+    double dphi;       // ||phi_n - phi_{n-1}||_inf
+    // conjugate-gradient memory
+    double rPr_prev;   // <r_{n-1}, P_{n-1} r_{n-1}>
+    // direction (after the preconditioner reductions)
+    double beta_cg, rho, pnorm, d1, d2, rPr_cur;
+    double aR_next;    // <phi_{n+1}, R phi_{n+1}> predicted by the step
+    int32_t restarted, dim;
+    // step (after the line search)
+    double theta, c_phi, c_p, c_L, c_Lp, dE;
+    // counters and flags
+    int64_t n, restarts, halvings, iters_fp32;
+    int32_t done, status, have_prev, linesearch_fail;
+    int32_t stagnant, nonfinite, force_gradient, precision;
+    // options copied per instance
+    double tol_res, tol_energy, theta_default;
+    int32_t method, beta_rule, max_halvings, precond;
+    int64_t max_iter;
+    // stagnation tracking (mixed precision)
+    double best_res;
+    int64_t best_n;
+    double switch_res;
+    int32_t stall_window, pad0;
+    // history
+    double* hist;      // device ring of rows of 8 doubles, nullable
+    int64_t hist_cap;
+};
+
+enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_LINESEARCH = -5, ST_NONFINITE = -4 };
+
+// ------------------------------------------------------------------------------------------------
+// Deterministic block reduction of K doubles: a masked xor-shuffle tree inside each wave (lanes
+// beyond the block's last thread contribute the identity), then the waves combined in a fixed
+// order.  Entry k is summed, or max-reduced when bit k of `maxmask` is set.  `red` is LDS scratch
+// of at least (blockDim/64) * K doubles; `out` is an LDS array of K doubles that holds the totals
+// for every thread on return.  Works for any block size; must be called by every thread.
+// ------------------------------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void block_reduce(double (&v)[K], double* red, double* out, unsigned maxmask) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    const int nact = min(64, (int)blockDim.x - wave * 64);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = v[k];
+        const bool mx = (maxmask >> k) & 1u;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_xor(s, off, 64);
+            if ((lane ^ off) >= nact) o = mx ? -1e300 : 0.0;
+            s = mx ? fmax(s, o) : s + o;
+        }
+        v[k] = s;
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const bool mx = (maxmask >> k) & 1u;
+        double s = red[k];
+        for (int w = 1; w < nw; ++w) {
+            const double o = red[w * K + k];
+            s = mx ? fmax(s, o) : s + o;
+        }
+        out[k] = s;
+    }
+    __syncthreads();
+}
+
+// "Last block done" ticket: every block calls this after writing its partials.  Returns true in
+// exactly one block (the last to arrive), after resetting the counter for the next launch, so
+// the pattern survives graph replays.  All threads of the block get the same answer.
+__device__ __forceinline__ bool last_block(unsigned int* counter, unsigned int nblocks, int* lds_flag) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int ticket = atomicAdd(counter, 1u);
+        int last = (ticket == nblocks - 1u);
+        if (last) atomicExch(counter, 0u);
+        *lds_flag = last;
+    }
+    __syncthreads();
+    bool last = *lds_flag != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+}  // namespace gpe

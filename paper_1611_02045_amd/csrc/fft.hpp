@@ -1,0 +1,148 @@
+// LDS-staged Stockham FFT of one line held across TPL = M/8 threads (8 points per thread).
+//
+// A line of M = 2^lg complex points (8 <= M <= 1024) is owned by TPL threads; thread t keeps the
+// eight points x[t + s*TPL], s = 0..7, in registers.  The transform is a sequence of Stockham
+// autosort stages: one radix-2 or radix-4 stage when lg is not a multiple of 3, then radix-8
+// stages.  Every stage reads its inputs from the positions t + s*TPL, so the first stage can
+// take its operands straight from a coalesced global load, and the last stage leaves
+// X[t + s*TPL] (natural frequency order) in the same registers.  Consequently a spectral
+// multiplier can be applied in registers and an inverse transform can follow with no LDS round
+// trip in between, and the inverse returns each thread the very positions it loaded -- so
+// pointwise epilogues see the original input in registers.  Between stages the data goes
+// through a padded LDS line buffer (one write, barrier, one read, barrier).
+//
+// The forward transform is unnormalised, sum_j x_j e^{-2 pi i jk/M}; the inverse uses e^{+...}
+// and is also unnormalised (callers fold 1/M into their multiplier), matching the expansions
+// of Section 3 of the paper.  Twiddles come from an LDS table tw[e] = exp(-2 pi i e/M) built
+// from FP64 host values.
+#pragma once
+
+#include "common.hpp"
+
+namespace gpe {
+
+// Padded LDS index: one spare slot per 8 points spreads the stride-Ns Stockham writes over banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
+// Padded length of one LDS line (odd, so neighbouring lines start in different banks).
+__host__ __device__ constexpr int line_stride(int M) { return M + (M >> 3) + 1; }
+
+// a * (DIR * i)
+template <typename T, int DIR>
+__host__ __device__ __forceinline__ C2<T> rot90(C2<T> a) {
+    return DIR < 0 ? mk(a.y, -a.x) : mk(-a.y, a.x);
+}
+
+template <typename T, int DIR>
+__host__ __device__ __forceinline__ void dft2(C2<T>& x0, C2<T>& x1) {
+    C2<T> a = add(x0, x1), b = sub(x0, x1);
+    x0 = a;
+    x1 = b;
+}
+
+// In-place 4-point DFT: (x0,x1,x2,x3) <- (X0,X1,X2,X3), X_k = sum_r x_r e^{DIR 2 pi i rk/4}.
+template <typename T, int DIR>
+__host__ __device__ __forceinline__ void dft4(C2<T>& x0, C2<T>& x1, C2<T>& x2, C2<T>& x3) {
+    C2<T> c0 = add(x0, x2), c2 = sub(x0, x2), c1 = add(x1, x3), c3 = rot90<T, DIR>(sub(x1, x3));
+    x0 = add(c0, c1);
+    x1 = add(c2, c3);
+    x2 = sub(c0, c1);
+    x3 = sub(c2, c3);
+}
+
+// In-place 8-point DFT on v[0..7] (natural order in and out): two radix-2 layers of 4 and the
+// twiddles e^{DIR 2 pi i r/8} in between, then two 4-point DFTs (even and odd outputs).
+template <typename T, int DIR>
+__host__ __device__ __forceinline__ void dft8(C2<T> (&v)[8]) {
+    const T c = (T)0.707106781186547524400844362104849039;
+    C2<T> a0 = add(v[0], v[4]), b0 = sub(v[0], v[4]);
+    C2<T> a1 = add(v[1], v[5]), b1 = sub(v[1], v[5]);
+    C2<T> a2 = add(v[2], v[6]), b2 = sub(v[2], v[6]);
+    C2<T> a3 = add(v[3], v[7]), b3 = sub(v[3], v[7]);
+    if (DIR < 0) {
+        b1 = mk(c * (b1.x + b1.y), c * (b1.y - b1.x));    // * e^{-i pi/4}
+        b2 = mk(b2.y, -b2.x);                            // * -i
+        b3 = mk(c * (b3.y - b3.x), -c * (b3.x + b3.y));  // * e^{-3 i pi/4}
+    } else {
+        b1 = mk(c * (b1.x - b1.y), c * (b1.x + b1.y));   // * e^{+i pi/4}
+        b2 = mk(-b2.y, b2.x);                            // * +i
+        b3 = mk(-c * (b3.x + b3.y), c * (b3.x - b3.y));  // * e^{+3 i pi/4}
+    }
+    dft4<T, DIR>(a0, a1, a2, a3);
+    dft4<T, DIR>(b0, b1, b2, b3);
+    v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
+    v[1] = b0; v[3] = b1; v[5] = b2; v[7] = b3;
+}
+
+// Read back v[s] = buf[t + s*TPL] after a stage's scattered write; barriers on both sides.
+template <typename T>
+__device__ __forceinline__ void exchange_read(C2<T> (&v)[8], const C2<T>* buf, int t, int TPL) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = buf[lpad(t + s * TPL)];
+    __syncthreads();
+}
+
+// Full line transform (see file comment).  All threads of the block must call it with the same
+// lg; `buf` is this thread's line region in LDS (line_stride(M) entries) and `tw` the table.
+template <typename T, int DIR>
+__device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, int t, int lg) {
+    const int TPL = 1 << (lg - 3);
+    const int rem = lg % 3;
+    const int n8 = lg / 3;
+    int lgNs = 0;
+    if (rem == 1) {
+        // radix-2 stage at Ns = 1: butterflies j = t + q*TPL on (v[q], v[q+4]); out[2j + r]
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dft2<T, DIR>(v[q], v[q + 4]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = t + q * TPL;
+            buf[lpad(2 * j)] = v[q];
+            buf[lpad(2 * j + 1)] = v[q + 4];
+        }
+        exchange_read(v, buf, t, TPL);
+        lgNs = 1;
+    } else if (rem == 2) {
+        // radix-4 stage at Ns = 1: butterflies j = t on v[0,2,4,6] and j = t + TPL on v[1,3,5,7]
+        dft4<T, DIR>(v[0], v[2], v[4], v[6]);
+        dft4<T, DIR>(v[1], v[3], v[5], v[7]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            buf[lpad(4 * t + r)] = v[2 * r];
+            buf[lpad(4 * (t + TPL) + r)] = v[2 * r + 1];
+        }
+        exchange_read(v, buf, t, TPL);
+        lgNs = 2;
+    }
+    for (int k = 0; k < n8; ++k) {
+        // radix-8 stage at Ns = 2^lgNs: butterfly j = t on v[r] (positions t + r*TPL)
+        if (lgNs > 0) {
+            const int jm = t & ((1 << lgNs) - 1);
+            const int step = jm << (lg - 3 - lgNs);  // jm * M / (8 Ns)
+#pragma unroll
+            for (int r = 1; r < 8; ++r) {
+                C2<T> w = tw[r * step];
+                if (DIR > 0) w.y = -w.y;
+                v[r] = mul(v[r], w);
+            }
+        }
+        dft8<T, DIR>(v);
+        if (k + 1 < n8) {
+            const int Ns = 1 << lgNs;
+            const int base = ((t >> lgNs) << (lgNs + 3)) + (t & (Ns - 1));
+#pragma unroll
+            for (int r = 0; r < 8; ++r) buf[lpad(base + r * Ns)] = v[r];
+            exchange_read(v, buf, t, TPL);
+        }
+        lgNs += 3;
+    }
+}
+
+// Copy the twiddle table of an M-point transform from global memory into LDS and barrier.
+template <typename T>
+__device__ __forceinline__ void load_twiddles(C2<T>* tw_lds, const C2<T>* tw_glob, int M) {
+    for (int i = threadIdx.x; i < M; i += blockDim.x) tw_lds[i] = tw_glob[i];
+    __syncthreads();
+}
+
+}  // namespace gpe

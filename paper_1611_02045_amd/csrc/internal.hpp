@@ -1,0 +1,85 @@
+// Internal host interfaces of libgpe (not part of the C ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/gpe.h"
+#include "common.hpp"
+
+namespace gpe {
+
+// Device buffer owned by a plan; grows on demand (never during graph capture).
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need) {
+        if (need <= bytes) return hipSuccess;
+        if (ptr) {
+            hipError_t e = hipFree(ptr);
+            if (e != hipSuccess) return e;
+            ptr = nullptr;
+            bytes = 0;
+        }
+        hipError_t e = hipMalloc(&ptr, need);
+        if (e == hipSuccess) bytes = need;
+        return e;
+    }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+};
+
+// Twiddle tables exp(-2 pi i e / M), e < M, for each axis, in both precisions.
+struct Twiddles {
+    DevBuf t64[3], t32[3];
+    const void* get(int axis, bool f64) const { return f64 ? t64[axis].ptr : t32[axis].ptr; }
+};
+
+hipError_t build_twiddles(const Geo& g, Twiddles& tw);
+Geo make_geo(const gpe_problem_t& p);
+
+// Reduction scratch: partial sums (doubles) and per-instance ticket counters (zeroed once).
+struct Reduce {
+    DevBuf parts;      // doubles
+    DevBuf counters;   // unsigned ints, one per instance per counter slot
+    DevBuf scalars;    // small device scalars (alpha, energy parts, ...)
+    int counter_slots = 0;
+};
+
+hipError_t reduce_init(Reduce& r, int instances, int slots, size_t part_doubles);
+
+// ---------------------------------------------------------------------------------------------
+// Operator launchers (ops.hip).  `f64` selects the precision of the fields (complex128/float64
+// vs complex64/float32).  Fields of B instances are stored back to back.  `tmp` is a workspace
+// of at least B*N complex values.
+// ---------------------------------------------------------------------------------------------
+hipError_t op_apply(const Geo& g, bool f64, int B, const Twiddles& tw, const void* f, const void* V,
+                    void* out, void* tmp, double beta, double omega, bool nonlinear, hipStream_t s);
+
+// Energy parts of one field: dst (device, 4 doubles) <- {kinetic, potential, interaction, rotation}.
+hipError_t op_energy(const Geo& g, bool f64, const Twiddles& tw, const void* phi, const void* V,
+                     double beta, double omega, Reduce& red, double* dst, hipStream_t s);
+
+// Preconditioner application with the shift read from device memory (*alpha_dev).
+hipError_t op_precond(const Geo& g, bool f64, const Twiddles& tw, int kind, const void* phi,
+                      const void* V, const double* alpha_dev, double beta, const void* r, void* out,
+                      void* tmp, hipStream_t s);
+
+// Minimum over the grid of alpha + V + beta |phi|^2 into *dst (device).
+hipError_t op_min_diag(const Geo& g, bool f64, const void* phi, const void* V, const double* alpha_dev,
+                       double beta, Reduce& red, double* dst, hipStream_t s);
+
+// lambda~ = kinetic + potential + 2 interaction from energy parts (device to device).
+hipError_t op_lambda_tilde(const double* parts, double* dst, hipStream_t s);
+
+// Energy gradient pieces: grad_phi = 2 h^d H phi (in place scaling of Hphi), grad_V = h^d |phi|^2.
+hipError_t op_scale_complex(const Geo& g, bool f64, void* x, double s, int64_t count, hipStream_t st);
+hipError_t op_density(const Geo& g, bool f64, const void* phi, void* out, double scale, hipStream_t s);
+
+// Thread-local error message.
+void set_error(const std::string& msg);
+
+}  // namespace gpe

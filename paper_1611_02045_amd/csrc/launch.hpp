@@ -1,0 +1,67 @@
+// Host-side launch helpers for directional passes.
+#pragma once
+
+#include <algorithm>
+
+#include "passes.hpp"
+
+namespace gpe {
+
+constexpr size_t kPassLdsBudget = 96 * 1024;
+
+inline size_t pass_lds_bytes_cb(int cb, int M, int C, int threads, int K) {
+    size_t b = (size_t)cb * ((size_t)M + (size_t)C * line_stride(M));
+    b = (b + 15) & ~(size_t)15;
+    b += sizeof(double) * (size_t)((((threads + 63) / 64) + 1) * (K > 0 ? K : 1) + 4);
+    return b;
+}
+
+// Lines per workgroup for a pass along AX: x-passes pack 256 threads of whole lines; strided
+// passes take enough adjacent lines that each row segment is 128 bytes (coalesced), capped by
+// the 1024-thread workgroup limit and by n_x.
+inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes) {
+    const int TPL = g.n[AX] / 8;
+    const int64_t lpf = lines_per_field(g, AX);
+    int C;
+    if (AX == 0) {
+        C = std::max(1, 256 / TPL);
+    } else {
+        C = std::max(1, 128 / complex_bytes);
+        C = std::min(C, std::max(1, 1024 / TPL));
+        C = std::min(C, g.n[0]);
+    }
+    while (C > 1 && (lpf % C) != 0) C >>= 1;
+    // keep the LDS footprint (twiddles + lines + reduction scratch) within budget
+    while (C > 1 && pass_lds_bytes_cb(complex_bytes, g.n[AX], C, C * TPL, 32) > kPassLdsBudget) C >>= 1;
+    return C;
+}
+
+inline int pass_blocks_per_field(const Geo& g, int AX, int complex_bytes) {
+    return (int)(lines_per_field(g, AX) / pass_lines_per_block(g, AX, complex_bytes));
+}
+
+// Launch one pass over B instances.  `pr` receives nb (blocks per instance) if the Op reduces.
+template <typename T, int AX, class Op>
+hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partials pr, hipStream_t s) {
+    const int cb = (int)sizeof(C2<T>);
+    const int C = pass_lines_per_block(g, AX, cb);
+    const int TPL = g.n[AX] / 8;
+    const int threads = C * TPL;
+    const int nb = (int)(lines_per_field(g, AX) / C);
+    pr.nb = nb;
+    const size_t lds = pass_lds_bytes<T>(g.n[AX], C, threads, Op::K);
+    auto kern = pass_kernel<T, AX, Op>;
+    static bool attr_set = false;  // one attribute call per instantiation
+    if (!attr_set) {
+        // Raise the dynamic-LDS cap once; a runtime that does not need it may refuse harmlessly.
+        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPassLdsBudget) !=
+            hipSuccess)
+            (void)hipGetLastError();
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)(nb * (int64_t)B)), dim3(threads), lds, s, g, C,
+                       (const C2<T>*)tw, op, pr);
+    return hipGetLastError();
+}
+
+}  // namespace gpe

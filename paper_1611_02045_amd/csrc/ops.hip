@@ -1,0 +1,411 @@
+// Standalone operators of the solver as chains of directional passes:
+//   * H_phi phi and L f = (T + V - omega L_z) f            (Sections 2-3)
+//   * the energy E(phi) and its parts                     (Section 2)
+//   * the preconditioners P_Delta, P_V, P_C, P_C1, P_C2   (Section 5.5)
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+#include "launch.hpp"
+
+namespace gpe {
+
+// Rotation coefficient of the directional symbol along AX for the line (i1, i2):
+// R = -omega L_z = i omega (x d_y - y d_x) acts as +omega y xi along x and -omega x mu along y.
+template <int AX>
+__device__ __forceinline__ double rot_coef(const Geo& g, const LineCtx& lc, double omega) {
+    if (g.dim < 2 || omega == 0.0) return 0.0;
+    if (AX == 0) return omega * coord_of(lc.i1, g.L[1], g.h[1]);
+    if (AX == 1) return -omega * coord_of(lc.i1, g.L[0], g.h[0]);
+    return 0.0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Directional part of L (and H): out = acc + F_a^{-1}[sigma_a F_a f], sigma_a = xi^2/2 + rot*xi,
+// and on the last axis also + (V + beta|f|^2) f (beta term only for the nonlinear H).
+// ---------------------------------------------------------------------------------------------
+template <typename T, int AX>
+struct OpApply {
+    static constexpr bool FWD = true, INV = true, FINAL = false;
+    static constexpr int K = 0;
+    static constexpr unsigned MAXMASK = 0;
+    const C2<T>* f;
+    const C2<T>* acc;  // nullable
+    C2<T>* out;
+    const T* V;        // used on the last axis
+    double beta, omega;
+    int last, nonlinear;
+    struct State { C2<T> f0[8]; };
+    __device__ bool skip(const Geo&, int) const { return false; }
+    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) st.f0[s] = v[s] = f[lc.at(s)];
+    }
+    __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
+                             const C2<T>*) const {
+        const double rot = rot_coef<AX>(g, lc, omega);
+        const double inv = 1.0 / lc.M;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const double xi = freq_of(lc.k(s), lc.M, g.L[AX]);
+            v[s] = scl(v[s], (T)((0.5 * xi * xi + rot * xi) * inv));
+        }
+    }
+    __device__ void store(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&)[1]) const {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int64_t i = lc.at(s);
+            C2<T> o = v[s];
+            if (acc) o = add(o, acc[i]);
+            if (last) {
+                T w = V[i - lc.off_b];
+                if (nonlinear) w += (T)beta * abs2(st.f0[s]);
+                o = add(o, scl(st.f0[s], w));
+            }
+            out[i] = o;
+        }
+    }
+    __device__ void finalize(const Geo&, int, const double*) const {}
+};
+
+template <typename T>
+static hipError_t apply_t(const Geo& g, int B, const Twiddles& tw, const void* f, const void* V, void* out,
+                          void* tmp, double beta, double omega, bool nl, hipStream_t s) {
+    const bool f64 = sizeof(T) == 8;
+    const C2<T>* F = (const C2<T>*)f;
+    Partials none{nullptr, nullptr, 0};
+    hipError_t e;
+    if (g.dim == 1) {
+        OpApply<T, 0> op{F, nullptr, (C2<T>*)out, (const T*)V, beta, omega, 1, nl};
+        return launch_pass<T, 0>(g, B, tw.get(0, f64), op, none, s);
+    }
+    // x-pass into tmp, then y (and z) passes accumulate; the last adds the pointwise part.
+    OpApply<T, 0> ox{F, nullptr, (C2<T>*)tmp, (const T*)V, beta, omega, 0, nl};
+    if ((e = launch_pass<T, 0>(g, B, tw.get(0, f64), ox, none, s)) != hipSuccess) return e;
+    if (g.dim == 2) {
+        OpApply<T, 1> oy{F, (const C2<T>*)tmp, (C2<T>*)out, (const T*)V, beta, omega, 1, nl};
+        return launch_pass<T, 1>(g, B, tw.get(1, f64), oy, none, s);
+    }
+    OpApply<T, 1> oy{F, (const C2<T>*)tmp, (C2<T>*)tmp, (const T*)V, beta, omega, 0, nl};
+    if ((e = launch_pass<T, 1>(g, B, tw.get(1, f64), oy, none, s)) != hipSuccess) return e;
+    OpApply<T, 2> oz{F, (const C2<T>*)tmp, (C2<T>*)out, (const T*)V, beta, omega, 1, nl};
+    return launch_pass<T, 2>(g, B, tw.get(2, f64), oz, none, s);
+}
+
+hipError_t op_apply(const Geo& g, bool f64, int B, const Twiddles& tw, const void* f, const void* V, void* out,
+                    void* tmp, double beta, double omega, bool nonlinear, hipStream_t s) {
+    return f64 ? apply_t<double>(g, B, tw, f, V, out, tmp, beta, omega, nonlinear, s)
+               : apply_t<float>(g, B, tw, f, V, out, tmp, beta, omega, nonlinear, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Energy: forward transforms only; Parseval turns <phi, F^{-1} sigma F phi> into
+// (1/M) sum sigma |F phi|^2 per line.  Sums: {kinetic, rotation, potential, quartic}.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int AX>
+struct OpEnergy {
+    static constexpr bool FWD = true, INV = false, FINAL = false;
+    static constexpr int K = 4;
+    static constexpr unsigned MAXMASK = 0;
+    const C2<T>* phi;
+    const T* V;
+    double omega;
+    struct State { C2<T> f0[8]; };
+    __device__ bool skip(const Geo&, int) const { return false; }
+    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) st.f0[s] = v[s] = phi[lc.at(s)];
+    }
+    __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[4], C2<T>*,
+                             const C2<T>*) const {
+        const double rot = rot_coef<AX>(g, lc, omega);
+        const double inv = 1.0 / lc.M;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const double xi = freq_of(lc.k(s), lc.M, g.L[AX]);
+            const double w = (double)abs2(v[s]) * inv;
+            acc[0] += 0.5 * xi * xi * w;
+            acc[1] += rot * xi * w;
+        }
+    }
+    __device__ void store(const Geo&, const LineCtx& lc, State& st, C2<T> (&)[8], double (&acc)[4]) const {
+        if (AX != 0) return;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int64_t i = lc.at(s);
+            const double r = (double)abs2(st.f0[s]);
+            acc[2] += (double)V[i] * r;
+            acc[3] += r * r;
+        }
+    }
+    __device__ void finalize(const Geo&, int, const double*) const {}
+};
+
+// Sum the per-block partials of up to three passes and scale into {kin, pot, inter, rot}.
+__global__ void k_energy_collect(const double* p0, int n0, const double* p1, int n1, const double* p2, int n2,
+                                 double cell, double beta, double* dst) {
+    __shared__ double red[16 * 4 + 8];
+    double v[4] = {0, 0, 0, 0};
+    const double* ps[3] = {p0, p1, p2};
+    const int ns[3] = {n0, n1, n2};
+    for (int q = 0; q < 3; ++q) {
+        if (!ps[q]) continue;
+        for (int blk = threadIdx.x; blk < ns[q]; blk += blockDim.x)
+            for (int k = 0; k < 4; ++k) v[k] += ps[q][(size_t)blk * 4 + k];
+    }
+    __shared__ double T4[4];
+    block_reduce<4>(v, red, T4, 0u);
+    if (threadIdx.x == 0) {
+        dst[0] = cell * T4[0];               // <phi, T phi>
+        dst[1] = cell * T4[2];               // <phi, V phi>
+        dst[2] = 0.5 * beta * cell * T4[3];  // beta/2 h^d sum |phi|^4
+        dst[3] = cell * T4[1];               // <phi, R phi> = -omega Re<phi, L_z phi>
+    }
+}
+
+template <typename T>
+static hipError_t energy_t(const Geo& g, const Twiddles& tw, const void* phi, const void* V, double beta,
+                           double omega, Reduce& red, double* dst, hipStream_t s) {
+    const bool f64 = sizeof(T) == 8;
+    const int cb = (int)sizeof(C2<T>);
+    const C2<T>* P = (const C2<T>*)phi;
+    double* parts = (double*)red.parts.ptr;
+    size_t off = 0;
+    const double* pp[3] = {nullptr, nullptr, nullptr};
+    int nn[3] = {0, 0, 0};
+    hipError_t e;
+    for (int ax = 0; ax < g.dim; ++ax) {
+        Partials pr{parts + off, nullptr, 0};
+        const int nb = pass_blocks_per_field(g, ax, cb);
+        if (ax == 0) e = launch_pass<T, 0>(g, 1, tw.get(0, f64), OpEnergy<T, 0>{P, (const T*)V, omega}, pr, s);
+        else if (ax == 1) e = launch_pass<T, 1>(g, 1, tw.get(1, f64), OpEnergy<T, 1>{P, (const T*)V, omega}, pr, s);
+        else e = launch_pass<T, 2>(g, 1, tw.get(2, f64), OpEnergy<T, 2>{P, (const T*)V, omega}, pr, s);
+        if (e != hipSuccess) return e;
+        pp[ax] = parts + off;
+        nn[ax] = nb;
+        off += (size_t)nb * 4;
+    }
+    hipLaunchKernelGGL(k_energy_collect, dim3(1), dim3(256), 0, s, pp[0], nn[0], pp[1], nn[1], pp[2], nn[2],
+                       g.cell, beta, dst);
+    return hipGetLastError();
+}
+
+hipError_t op_energy(const Geo& g, bool f64, const Twiddles& tw, const void* phi, const void* V, double beta,
+                     double omega, Reduce& red, double* dst, hipStream_t s) {
+    return f64 ? energy_t<double>(g, tw, phi, V, beta, omega, red, dst, s)
+               : energy_t<float>(g, tw, phi, V, beta, omega, red, dst, s);
+}
+
+__global__ void k_lambda_tilde(const double* parts, double* dst) {
+    if (threadIdx.x == 0) *dst = parts[0] + parts[1] + 2.0 * parts[2];
+}
+
+hipError_t op_lambda_tilde(const double* parts, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_lambda_tilde, dim3(1), dim3(64), 0, s, parts, dst);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Preconditioners.  Scaling kinds: 0 none, 1 by (alpha + V + beta|phi|^2)^{-1/2}, 2 by its inverse.
+// The spectral multiplier 1/(alpha + |k|^2/2) (with the 1/N of the inverse transforms) is applied
+// in the pass that does both the forward and the inverse transform (the last axis).
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T pv_scale(int kind, double alpha, T V, T rho, double beta) {
+    const double d = alpha + (double)V + beta * (double)rho;
+    return kind == 1 ? (T)(1.0 / sqrt(d)) : (T)(1.0 / d);
+}
+
+template <typename T, int AX, bool F, bool I>
+struct OpPre {
+    static constexpr bool FWD = F, INV = I, FINAL = false;
+    static constexpr int K = 0;
+    static constexpr unsigned MAXMASK = 0;
+    const C2<T>* in;
+    C2<T>* out;
+    const C2<T>* phi;
+    const T* V;
+    const double* alpha;
+    double beta;
+    int pre, post;
+    struct State {};
+    __device__ bool skip(const Geo&, int) const { return false; }
+    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
+        const double a = *alpha;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int64_t i = lc.at(s);
+            v[s] = in[i];
+            if (pre) v[s] = scl(v[s], pv_scale<T>(pre, a, V[i], abs2(phi[i]), beta));
+        }
+    }
+    __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
+                             const C2<T>*) const {
+        if (!(F && I)) return;
+        const double a = *alpha;
+        // frequencies of the other (already transformed) axes
+        double ko = 0.0;
+        if (AX == 1) {
+            const double xi = freq_of(lc.i1, g.n[0], g.L[0]);
+            ko = xi * xi;
+        } else if (AX == 2) {
+            const double xi = freq_of(lc.i1, g.n[0], g.L[0]);
+            const double mu = freq_of(lc.i2, g.n[1], g.L[1]);
+            ko = xi * xi + mu * mu;
+        }
+        const double invN = 1.0 / (double)g.N;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const double k = freq_of(lc.k(s), lc.M, g.L[AX]);
+            v[s] = scl(v[s], (T)(invN / (a + 0.5 * (ko + k * k))));
+        }
+    }
+    __device__ void store(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1]) const {
+        const double a = post ? *alpha : 0.0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int64_t i = lc.at(s);
+            C2<T> o = v[s];
+            if (post) o = scl(o, pv_scale<T>(post, a, V[i], abs2(phi[i]), beta));
+            out[i] = o;
+        }
+    }
+    __device__ void finalize(const Geo&, int, const double*) const {}
+};
+
+template <typename T>
+__global__ void k_precond_diag(const C2<T>* r, C2<T>* out, const C2<T>* phi, const T* V, const double* alpha,
+                               double beta, int kind, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    C2<T> v = r[i];
+    if (kind == GPE_P_POTENTIAL) v = scl(v, pv_scale<T>(2, *alpha, V[i], abs2(phi[i]), beta));
+    out[i] = v;
+}
+
+// Full multi-dimensional P_Delta with pre/post scalings: x forward, middle axes, x inverse.
+template <typename T>
+static hipError_t kinetic_chain(const Geo& g, const Twiddles& tw, const C2<T>* r, C2<T>* out, C2<T>* tmp,
+                                const C2<T>* phi, const T* V, const double* alpha, double beta, int pre,
+                                int post, hipStream_t s) {
+    const bool f64 = sizeof(T) == 8;
+    Partials none{nullptr, nullptr, 0};
+    hipError_t e;
+    if (g.dim == 1) {
+        OpPre<T, 0, true, true> op{r, out, phi, V, alpha, beta, pre, post};
+        return launch_pass<T, 0>(g, 1, tw.get(0, f64), op, none, s);
+    }
+    OpPre<T, 0, true, false> x1{r, tmp, phi, V, alpha, beta, pre, 0};
+    if ((e = launch_pass<T, 0>(g, 1, tw.get(0, f64), x1, none, s)) != hipSuccess) return e;
+    if (g.dim == 2) {
+        OpPre<T, 1, true, true> y{tmp, tmp, phi, V, alpha, beta, 0, 0};
+        if ((e = launch_pass<T, 1>(g, 1, tw.get(1, f64), y, none, s)) != hipSuccess) return e;
+    } else {
+        OpPre<T, 1, true, false> y1{tmp, tmp, phi, V, alpha, beta, 0, 0};
+        if ((e = launch_pass<T, 1>(g, 1, tw.get(1, f64), y1, none, s)) != hipSuccess) return e;
+        OpPre<T, 2, true, true> z{tmp, tmp, phi, V, alpha, beta, 0, 0};
+        if ((e = launch_pass<T, 2>(g, 1, tw.get(2, f64), z, none, s)) != hipSuccess) return e;
+        OpPre<T, 1, false, true> y2{tmp, tmp, phi, V, alpha, beta, 0, 0};
+        if ((e = launch_pass<T, 1>(g, 1, tw.get(1, f64), y2, none, s)) != hipSuccess) return e;
+    }
+    OpPre<T, 0, false, true> x2{tmp, out, phi, V, alpha, beta, 0, post};
+    return launch_pass<T, 0>(g, 1, tw.get(0, f64), x2, none, s);
+}
+
+template <typename T>
+static hipError_t precond_t(const Geo& g, const Twiddles& tw, int kind, const void* phi, const void* V,
+                            const double* alpha, double beta, const void* r, void* out, void* tmp, hipStream_t s) {
+    const C2<T>* R = (const C2<T>*)r;
+    C2<T>* O = (C2<T>*)out;
+    const C2<T>* P = (const C2<T>*)phi;
+    const T* Vt = (const T*)V;
+    if (kind == GPE_P_NONE || kind == GPE_P_POTENTIAL) {
+        const int64_t N = g.N;
+        hipLaunchKernelGGL(k_precond_diag<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, R, O, P, Vt, alpha,
+                           beta, kind, N);
+        return hipGetLastError();
+    }
+    int pre = 0, post = 0;
+    if (kind == GPE_P_COMBINED) pre = post = 1;  // P_V^{1/2} P_Delta P_V^{1/2}
+    if (kind == GPE_P_C1) post = 2;              // P_V P_Delta
+    if (kind == GPE_P_C2) pre = 2;               // P_Delta P_V
+    return kinetic_chain<T>(g, tw, R, O, (C2<T>*)tmp, P, Vt, alpha, beta, pre, post, s);
+}
+
+hipError_t op_precond(const Geo& g, bool f64, const Twiddles& tw, int kind, const void* phi, const void* V,
+                      const double* alpha_dev, double beta, const void* r, void* out, void* tmp, hipStream_t s) {
+    return f64 ? precond_t<double>(g, tw, kind, phi, V, alpha_dev, beta, r, out, tmp, s)
+               : precond_t<float>(g, tw, kind, phi, V, alpha_dev, beta, r, out, tmp, s);
+}
+
+// Minimum of alpha + V + beta |phi|^2 (SPD check of P_V), two-level deterministic reduction.
+template <typename T>
+__global__ void k_min_diag(const C2<T>* phi, const T* V, const double* alpha, double beta, int64_t N,
+                           double* parts) {
+    __shared__ double red[16 + 4];
+    double m[1] = {1e300};
+    const double a = *alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        m[0] = fmin(m[0], a + (double)V[i] + beta * (double)abs2(phi[i]));
+    m[0] = -m[0];
+    __shared__ double o1[1];
+    block_reduce<1>(m, red, o1, 1u);
+    if (threadIdx.x == 0) parts[blockIdx.x] = -o1[0];
+}
+
+__global__ void k_min_collect(const double* parts, int n, double* dst) {
+    if (threadIdx.x == 0) {
+        double m = parts[0];
+        for (int i = 1; i < n; ++i) m = fmin(m, parts[i]);
+        *dst = m;
+    }
+}
+
+hipError_t op_min_diag(const Geo& g, bool f64, const void* phi, const void* V, const double* alpha_dev,
+                       double beta, Reduce& red, double* dst, hipStream_t s) {
+    const int blocks = 256;
+    double* parts = (double*)red.parts.ptr;
+    if (f64)
+        hipLaunchKernelGGL(k_min_diag<double>, dim3(blocks), dim3(256), 0, s, (const C2<double>*)phi,
+                           (const double*)V, alpha_dev, beta, g.N, parts);
+    else
+        hipLaunchKernelGGL(k_min_diag<float>, dim3(blocks), dim3(256), 0, s, (const C2<float>*)phi,
+                           (const float*)V, alpha_dev, beta, g.N, parts);
+    hipLaunchKernelGGL(k_min_collect, dim3(1), dim3(64), 0, s, parts, blocks, dst);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Small pointwise helpers.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_scale_complex(C2<T>* x, T s, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = scl(x[i], s);
+}
+
+template <typename T>
+__global__ void k_density(const C2<T>* phi, T* out, T scale, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = scale * abs2(phi[i]);
+}
+
+hipError_t op_scale_complex(const Geo&, bool f64, void* x, double s, int64_t count, hipStream_t st) {
+    const unsigned blocks = (unsigned)((count + 255) / 256);
+    if (f64) hipLaunchKernelGGL(k_scale_complex<double>, dim3(blocks), dim3(256), 0, st, (C2<double>*)x, s, count);
+    else hipLaunchKernelGGL(k_scale_complex<float>, dim3(blocks), dim3(256), 0, st, (C2<float>*)x, (float)s, count);
+    return hipGetLastError();
+}
+
+hipError_t op_density(const Geo& g, bool f64, const void* phi, void* out, double scale, hipStream_t s) {
+    const unsigned blocks = (unsigned)((g.N + 255) / 256);
+    if (f64)
+        hipLaunchKernelGGL(k_density<double>, dim3(blocks), dim3(256), 0, s, (const C2<double>*)phi, (double*)out,
+                           scale, g.N);
+    else
+        hipLaunchKernelGGL(k_density<float>, dim3(blocks), dim3(256), 0, s, (const C2<float>*)phi, (float*)out,
+                           (float)scale, g.N);
+    return hipGetLastError();
+}
+
+}  // namespace gpe

@@ -1,0 +1,164 @@
+// Generic directional pass: one workgroup transforms C grid lines along one axis.
+//
+// Every hot operator of the solver is a chain of such passes (Section 3: the discrete
+// operators act as 1-D transforms along x at fixed y, along y at fixed x, ...).  A pass is
+//   decode line -> Op::load (prologue, fills the 8 registers) -> forward FFT (optional)
+//   -> Op::spectral (multiplier and spectral reductions) -> inverse FFT (optional)
+//   -> Op::store (epilogue: combine, write, pointwise reductions)
+//   -> deterministic block reduction of Op::K sums into per-block partials
+//   -> optionally, in the last block of each instance, Op::finalize (FP64 scalar logic).
+// Field layout: x fastest; a batch of B equally sized instances is stored back to back.  For the
+// x axis consecutive lanes walk along one line (stride 1, coalesced); for y and z consecutive
+// lanes walk across C adjacent lines (adjacent x, coalesced), and each thread keeps its 8
+// points strided along the line.
+#pragma once
+
+#include "fft.hpp"
+
+namespace gpe {
+
+struct LineCtx {
+    int t;          // position of this thread within its line, [0, TPL)
+    int c;          // line within the block
+    int b;          // instance (batch) index
+    int i1, i2;     // indices of the line along the other axes (x-pass: y,z; y-pass: x,z; z-pass: x,y)
+    int lg, M, TPL;
+    int64_t base;   // offset of point 0 of the line in the batched field
+    int64_t stride; // distance between consecutive points of the line
+    int64_t off_b;  // b * N
+    __device__ __forceinline__ int64_t at(int s) const { return base + (int64_t)(t + s * TPL) * stride; }
+    __device__ __forceinline__ int k(int s) const { return t + s * TPL; }
+};
+
+// Number of lines of one instance for a pass along axis AX.
+__host__ __device__ inline int64_t lines_per_field(const Geo& g, int AX) {
+    return g.N / g.n[AX];
+}
+
+template <int AX>
+__device__ __forceinline__ LineCtx decode_line(const Geo& g, int C) {
+    LineCtx lc;
+    lc.lg = g.lg[AX];
+    lc.M = 1 << lc.lg;
+    lc.TPL = lc.M >> 3;
+    const int tid = threadIdx.x;
+    if (AX == 0) {
+        lc.c = tid >> (lc.lg - 3);
+        lc.t = tid & (lc.TPL - 1);
+    } else {
+        lc.c = tid & (C - 1);
+        lc.t = tid / C;
+    }
+    const int64_t line = (int64_t)blockIdx.x * C + lc.c;
+    const int64_t lpf = lines_per_field(g, AX);
+    lc.b = (int)(line / lpf);
+    const int64_t lf = line - (int64_t)lc.b * lpf;
+    lc.off_b = (int64_t)lc.b * g.N;
+    const int nx = g.n[0], ny = g.n[1];
+    if (AX == 0) {
+        lc.i1 = (int)(lf % ny);
+        lc.i2 = (int)(lf / ny);
+        lc.base = lc.off_b + lf * nx;
+        lc.stride = 1;
+    } else if (AX == 1) {
+        lc.i1 = (int)(lf % nx);
+        lc.i2 = (int)(lf / nx);
+        lc.base = lc.off_b + (int64_t)lc.i2 * nx * ny + lc.i1;
+        lc.stride = nx;
+    } else {
+        lc.i1 = (int)(lf % nx);
+        lc.i2 = (int)(lf / nx);
+        lc.base = lc.off_b + (int64_t)lc.i2 * nx + lc.i1;
+        lc.stride = (int64_t)nx * ny;
+    }
+    return lc;
+}
+
+// Dynamic LDS layout of a pass: [twiddles M][lines C * line_stride(M)][reduction scratch].
+template <typename T>
+__host__ __device__ inline size_t pass_lds_bytes(int M, int C, int threads, int K) {
+    size_t b = sizeof(C2<T>) * ((size_t)M + (size_t)C * line_stride(M));
+    b = (b + 15) & ~(size_t)15;
+    b += sizeof(double) * (size_t)((((threads + 63) / 64) + 1) * (K > 0 ? K : 1) + 4);
+    return b;
+}
+
+// Partial-sum buffers for reducing passes: parts[b][block][K] (FP64) and one ticket counter per
+// instance.  `nb` is the number of blocks per instance.
+struct Partials {
+    double* parts;
+    unsigned int* counters;
+    int nb;
+};
+
+// Sum K partials of instance b over its nb blocks with all threads of the (last) block, in a
+// fixed order.  `red` is block_reduce scratch; `out` (LDS, K doubles) receives the totals.
+template <int K>
+__device__ __forceinline__ void reduce_partials(const double* parts, int nb, double* red, double* out,
+                                                unsigned maxmask) {
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = ((maxmask >> k) & 1u) ? -1e300 : 0.0;
+    for (int blk = threadIdx.x; blk < nb; blk += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double p = parts[(size_t)blk * K + k];
+            acc[k] = ((maxmask >> k) & 1u) ? fmax(acc[k], p) : acc[k] + p;
+        }
+    }
+    block_reduce<K>(acc, red, out, maxmask);
+}
+
+// The pass kernel.  Op must provide:
+//   static constexpr bool FWD, INV;  static constexpr int K;  static constexpr bool FINAL;
+//   static constexpr unsigned MAXMASK;  (bit k set: sum k is a max-reduction of non-negatives)
+//   struct State;   __device__ bool skip(const Geo&, int b) const;
+//   __device__ void load(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
+//   __device__ void spectral(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K],
+//                            C2<T>* buf, const C2<T>* tw) const;   (buf/tw: to transform more lines)
+//   __device__ void store(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
+//   __device__ void finalize(const Geo&, int b, const double* totals) const;   // if FINAL
+// K sums are accumulated per thread in FP64 and reduced deterministically.
+template <typename T, int AX, class Op>
+__global__ __launch_bounds__(1024) void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op,
+                                                    Partials pr) {
+    extern __shared__ double4 smem_raw[];
+    const LineCtx lc = decode_line<AX>(g, C);
+    if (op.skip(g, lc.b)) return;  // uniform per block: all lines of a block share one instance
+    C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
+    C2<T>* buf = tw + lc.M + (size_t)lc.c * line_stride(lc.M);
+    size_t off = sizeof(C2<T>) * ((size_t)lc.M + (size_t)C * line_stride(lc.M));
+    off = (off + 15) & ~(size_t)15;
+    double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem_raw) + off);
+    load_twiddles(tw, twg, lc.M);
+
+    typename Op::State st;
+    C2<T> v[8];
+    double acc[Op::K > 0 ? Op::K : 1];
+#pragma unroll
+    for (int k = 0; k < (Op::K > 0 ? Op::K : 1); ++k) acc[k] = 0.0;
+
+    op.load(g, lc, st, v, acc);
+    if (Op::FWD) fft_line<T, -1>(v, buf, tw, lc.t, lc.lg);
+    op.spectral(g, lc, st, v, acc, buf, tw);
+    if (Op::INV) fft_line<T, +1>(v, buf, tw, lc.t, lc.lg);
+    op.store(g, lc, st, v, acc);
+
+    if constexpr (Op::K > 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double* outK = red + (size_t)nw * Op::K;
+        block_reduce<Op::K>(acc, red, outK, Op::MAXMASK);
+        const int blk_in_inst = (int)(blockIdx.x % (unsigned)pr.nb);
+        double* P = pr.parts + ((size_t)lc.b * pr.nb + blk_in_inst) * Op::K;
+        for (int k = threadIdx.x; k < Op::K; k += blockDim.x) P[k] = outK[k];
+        if constexpr (Op::FINAL) {
+            int* flag = reinterpret_cast<int*>(outK + Op::K);
+            if (last_block(pr.counters + lc.b, (unsigned)pr.nb, flag)) {
+                reduce_partials<Op::K>(pr.parts + (size_t)lc.b * pr.nb * Op::K, pr.nb, red, outK, Op::MAXMASK);
+                op.finalize(g, lc.b, outK);
+            }
+        }
+    }
+}
+
+}  // namespace gpe

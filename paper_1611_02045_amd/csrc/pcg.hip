@@ -1,0 +1,666 @@
+// One iteration of the projected preconditioned gradient / conjugate gradient method on the
+// unit sphere (Algorithms 1-2 with the step control of Sections 5.1-5.2), as a short chain of
+// fused passes over the fields of B independent instances of one grid:
+//
+//   A  r = L phi + beta|phi|^2 phi - lambda phi, ||r||_inf, preconditioner (Section 5.5)
+//        [x pass: residual + P_V^{1/2} prologue + forward x]  [middle passes: y (z), multiplier
+//        1/(lambda~ + |k|^2/2)]  [x pass: inverse x + P_V^{1/2} epilogue + CG reductions]
+//   B  p = -P r + beta_cg p_{n-1} - Re<d, phi> phi, phat = p/||p||, L phat  (Section 5.2)
+//        [x pass, y/z passes; the last one also forms every line-search sum]
+//   C  phi <- (cos t phi + sin t phat)/nu,  L phi <- (cos t L phi + sin t L phat)/nu  (linearity
+//        of L: no transform of phi_{n+1} is needed), fresh <phi, L phi>, sum|phi|^4, ||phi||^2.
+//
+// Scalar logic runs in the last workgroup of each reducing kernel (FP64, deterministic order):
+// the convergence test after A's first pass, beta_cg and the descent test after A, the step
+// after B, and the new lambda / lambda~ / E after C.  Every kernel returns at once for
+// instances whose `done` flag is set, so surplus iterations queued after convergence are no-ops.
+//
+// Line search: E(cos t phi + sin t phat) - E(phi) is a trigonometric polynomial in t whose
+// coefficients are the reductions <phat, L phat>, <phi, L phat>, <phi, L phi> and sums of
+// A = |phi|^2, B = Re(conj(phi) phat), C = |phat|^2 products; the trial steps of the paper's
+// heuristic are therefore evaluated exactly, for any number of trials, from one pass.
+#include <cmath>
+
+#include "internal.hpp"
+#include "launch.hpp"
+#include "pcg.hpp"
+
+namespace gpe {
+
+// ---------------------------------------------------------------------------------------------
+// Shared pieces
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double pv_diag(const Scal& S, double V, double rho) {
+    return S.lamt + V + S.beta * rho;
+}
+
+template <typename T>
+__device__ __forceinline__ T pscale(int kind, double d) {
+    return kind == 1 ? (T)(1.0 / sqrt(d)) : kind == 2 ? (T)(1.0 / d) : (T)1;
+}
+
+// Rotation coefficient of the directional symbol (see ops.hip) from per-instance geometry.
+template <int AX>
+__device__ __forceinline__ double rot_coef_s(const Scal& S, const LineCtx& lc) {
+    if (S.dim < 2 || S.omega == 0.0) return 0.0;
+    if (AX == 0) return S.omega * coord_of(lc.i1, S.L[1], S.h[1]);
+    if (AX == 1) return -S.omega * coord_of(lc.i1, S.L[0], S.h[0]);
+    return 0.0;
+}
+
+__device__ __forceinline__ void hist_row(Scal& S, int col, double v) {
+    if (S.hist && S.n < S.hist_cap) S.hist[S.n * 8 + col] = v;
+}
+
+// Convergence test at the top of iteration n (Section 5.3; reading: ||r_n||_inf <= tol).
+__device__ void fin_residual(Scal& S, double res, double nonfinite) {
+    if (threadIdx.x == 0) {
+        S.res = res;
+        hist_row(S, 0, (double)S.n);
+        hist_row(S, 1, S.E);
+        hist_row(S, 2, S.lam);
+        hist_row(S, 3, res);
+        if (nonfinite > 0.0 || !isfinite(res) || !isfinite(S.E)) {
+            S.status = ST_NONFINITE;
+            S.nonfinite = 1;
+            S.done = 1;
+        } else if (res <= S.tol_res) {
+            S.status = ST_OK;
+            S.done = 1;
+        } else if (S.tol_energy > 0.0 && S.n > 0 && fabs(S.E - S.E_prev) <= S.tol_energy) {
+            S.status = ST_OK;
+            S.done = 1;
+        } else if (S.n >= S.max_iter) {
+            S.status = ST_NOT_CONVERGED;
+            S.done = 1;
+        } else if (S.stall_window > 0) {
+            // mixed precision: leave the FP32 phase when the residual stops improving
+            if (res < S.best_res * (1.0 - 1e-3)) {
+                S.best_res = res;
+                S.best_n = S.n;
+            } else if (S.n - S.best_n >= S.stall_window) {
+                S.stagnant = 1;
+                S.status = ST_OK;
+                S.done = 1;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// CG direction from the A-phase sums (Section 5.2, readings: beta_0 = 0, PR+ with the stored
+// denominator, restart when Re<r, p> >= 0).
+__device__ void fin_direction(Scal& S, const double* t) {
+    if (threadIdx.x == 0 && !S.done) {
+        const double w = S.cell;
+        const double rPr = w * t[A_RPR], rpPr = w * t[A_RPPR], Prphi = w * t[A_PRPHI], PrPr = w * t[A_PRPR];
+        const double Prpp = w * t[A_PRPP], rpp = w * t[A_RPP], ppphi = w * t[A_PPPHI], pppp = w * t[A_PPPP];
+        const double rphi = w * t[A_RPHI], phiphi = w * t[A_PHIPHI];
+        double beta = 0.0;
+        if (S.method == 1 && S.have_prev && S.rPr_prev > 0.0) {
+            beta = S.beta_rule == 1 ? rPr / S.rPr_prev : fmax((rPr - rpPr) / S.rPr_prev, 0.0);
+        }
+        double rho = -Prphi + beta * ppphi;                 // Re<d, phi>
+        double rp = -rPr + beta * rpp - rho * rphi;         // Re<r, p>
+        S.restarted = 0;
+        if (!(rp < 0.0)) {  // not a descent direction: gradient step
+            beta = 0.0;
+            rho = -Prphi;
+            rp = -rPr - rho * rphi;
+            S.restarted = 1;
+            S.restarts += 1;
+        }
+        const double dd = PrPr - 2.0 * beta * Prpp + beta * beta * pppp;
+        const double pp = dd - 2.0 * rho * rho + rho * rho * phiphi;
+        S.beta_cg = beta;
+        S.rho = rho;
+        S.pnorm = sqrt(fmax(pp, 0.0));
+        S.rPr_cur = rPr;
+        S.d1 = rp;
+        if (!(S.pnorm > 0.0) || !isfinite(S.pnorm) || !isfinite(rPr)) {
+            S.status = ST_NONFINITE;
+            S.nonfinite = 1;
+            S.done = 1;
+        }
+        hist_row(S, 5, beta);
+        hist_row(S, 7, (double)S.restarted);
+    }
+    __syncthreads();
+}
+
+// Energy change along the great circle, from the B-phase sums (see the file comment).
+__device__ __forceinline__ double delta_energy(double c, double s, double a, double b, double cc, double beta,
+                                               const double* q) {
+    const double quad = s * s * (cc - a) + 2.0 * c * s * b;
+    const double quart = 4.0 * c * s * q[0] + 2.0 * s * s * q[1] + 4.0 * c * c * s * s * q[2] +
+                         4.0 * c * s * s * s * q[3] + s * s * s * s * q[4];
+    return quad + 0.5 * beta * quart;
+}
+
+// Step selection (Section 5.1 heuristic; readings: theta_opt = -E'(0)/E''(0) when E''(0) > 0,
+// else theta_default; clamp to (0, pi/2]; halve until E decreases, at most max_halvings times).
+__device__ void fin_step(Scal& S, const double* t) {
+    if (threadIdx.x == 0 && !S.done) {
+        const double w = S.cell;
+        const double cR = w * t[B_CR], aR = w * t[B_AR], bR = w * t[B_BR];
+        const double cc = w * t[B_C], b = w * t[B_B];
+        const double SAA = w * t[B_AA], SAB = w * t[B_AB], SACA = w * t[B_ACA], SCACA = w * t[B_CACA];
+        const double SCAB = w * t[B_CAB], SBB = w * t[B_BB], SAC = w * t[B_AC], SB = w * t[B_SB], SC = w * t[B_SC];
+        const double nonfinite = t[B_NF];
+        const double beta = S.beta;
+        // E'(0) = 2 Re<H phi, phat>, E''(0) = 2 (<phat, H phat> + 2 beta sum (Re conj(phi) phat)^2 - lambda)
+        const double d1 = 2.0 * (b + beta * SAB);
+        const double d2 = 2.0 * (cc + beta * SAC + 2.0 * beta * SBB - S.lam);
+        double th = d2 > 0.0 ? -d1 / d2 : S.theta_default;
+        th = fmin(fmax(th, 0.0), 1.5707963267948966);
+        const double q[5] = {SAB, SACA, SBB, SCAB, SCACA};
+        double acc_t = -1.0, dE = 0.0;
+        int j = 0;
+        for (; j <= S.max_halvings; ++j) {
+            const double tj = th * ldexp(1.0, -j);
+            if (!(tj > 0.0)) break;
+            const double e = delta_energy(cos(tj), sin(tj), S.a, b, cc, beta, q);
+            if (e < 0.0) {
+                acc_t = tj;
+                dE = e;
+                break;
+            }
+        }
+        S.d2 = d2;
+        if (nonfinite > 0.0 || !isfinite(d1) || !isfinite(d2)) {
+            S.status = ST_NONFINITE;
+            S.nonfinite = 1;
+            S.done = 1;
+        } else if (acc_t < 0.0) {
+            // no trial decreased the energy: in FP32 this ends the phase (switch to FP64)
+            S.linesearch_fail = 1;
+            if (S.precision == 1) {
+                S.stagnant = 1;
+                S.status = ST_OK;
+            } else {
+                S.status = ST_LINESEARCH;
+            }
+            S.done = 1;
+        } else {
+            const double c = cos(acc_t), s = sin(acc_t);
+            const double n2 = c * c * S.nrm2 + 2.0 * c * s * SB + s * s * SC;
+            const double nu = 1.0 / sqrt(n2);
+            S.theta = acc_t;
+            S.dE = dE;
+            S.halvings += j;
+            S.c_phi = nu * c;
+            S.c_p = nu * s / S.pnorm;
+            S.c_L = nu * c;
+            S.c_Lp = nu * s;
+            S.aR_next = nu * nu * (c * c * aR + 2.0 * c * s * bR + s * s * cR);
+            hist_row(S, 4, acc_t);
+            hist_row(S, 6, (double)j);
+        }
+        (void)SAA;
+    }
+    __syncthreads();
+}
+
+// New scalars of phi_{n+1} after the update (Section 2: lambda = <H phi, phi>, E; Section 5.5:
+// lambda~ = <phi, (T + V) phi> + beta h^d sum |phi|^4).
+__device__ void fin_update(Scal& S, const double* t) {
+    if (threadIdx.x == 0 && !S.done) {
+        const double w = S.cell;
+        const double a = w * t[C_A], q4 = w * t[C_Q4], n2 = w * t[C_N2];
+        S.a = a;
+        S.q4 = q4;
+        S.nrm2 = n2;
+        S.dphi = t[C_DPHI];
+        S.aR = S.aR_next;
+        S.lam = a + S.beta * q4;
+        S.lamt = a - S.aR + S.beta * q4;
+        S.E_prev = S.E;
+        S.E = a + 0.5 * S.beta * q4;
+        S.rPr_prev = S.rPr_cur;
+        S.have_prev = 1;
+        S.n += 1;
+        if (S.precision == 1) S.iters_fp32 += 1;
+        if (t[C_NF] > 0.0 || !isfinite(S.E)) {
+            S.status = ST_NONFINITE;
+            S.nonfinite = 1;
+            S.done = 1;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Phase A, first pass (x): residual, ||r||_inf, P_V^{1/2} (or P_V) prologue, forward x.
+// With ONE (1-D) the pass also applies the multiplier, the inverse and the epilogue, i.e. the
+// whole preconditioner and the CG reductions.
+// ---------------------------------------------------------------------------------------------
+template <typename T, bool ONE>
+struct OpResid {
+    static constexpr bool FWD = true, INV = ONE, FINAL = true;
+    static constexpr int K = A_K;
+    static constexpr unsigned MAXMASK = A_MAXMASK;
+    IterFields<T> f;
+    Scal* S;
+    int pre, post;
+    struct State {
+        C2<T> ph[ONE ? 8 : 1];
+        C2<T> r[ONE ? 8 : 1];
+        double d[ONE ? 8 : 1];
+    };
+    __device__ bool skip(const Geo&, int b) const { return S[b].done != 0; }
+    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
+        const Scal& s = S[lc.b];
+        const T lam = (T)s.lam, beta = (T)s.beta;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = lc.at(q);
+            const C2<T> ph = f.phi[i];
+            const C2<T> lp = f.Lphi[i];
+            const T V = f.V[i];
+            const T rho = abs2(ph);
+            const C2<T> r = add(lp, scl(ph, beta * rho - lam));
+            f.r[i] = r;
+            res_sums<T>(acc, r);
+            const double d = pv_diag(s, (double)V, (double)rho);
+            v[q] = scl(r, pscale<T>(pre, d));
+            if constexpr (ONE) {
+                st.ph[q] = ph;
+                st.r[q] = r;
+                st.d[q] = d;
+            }
+        }
+    }
+    __device__ void spectral(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K], C2<T>*,
+                             const C2<T>*) const {
+        if constexpr (ONE) {
+            const Scal& s = S[lc.b];
+            const double invN = 1.0 / lc.M;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double k = freq_of(lc.k(q), lc.M, s.L[0]);
+                v[q] = scl(v[q], (T)(invN / (s.lamt + 0.5 * k * k)));
+            }
+        }
+        (void)acc;
+    }
+    __device__ void store(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K]) const {
+        if constexpr (!ONE) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) f.w[lc.at(q)] = v[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t i = lc.at(q);
+                const C2<T> pr = scl(v[q], pscale<T>(post, st.d[q]));
+                f.pr[i] = pr;
+                cg_sums<T>(acc, st.r[q], pr, f.rp[i], f.pp[i], st.ph[q]);
+            }
+        }
+    }
+    __device__ void finalize(const Geo&, int b, const double* t) const {
+        fin_residual(S[b], t[A_RES], t[A_NF]);
+        if constexpr (ONE) fin_direction(S[b], t);
+    }
+};
+
+// ---------------------------------------------------------------------------------------------
+// Phase A, middle passes (y, z): forward and/or inverse transform with the kinetic multiplier
+// 1/(lambda~ + |k|^2/2) (with the 1/N of the inverse transforms) on the pass that does both.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int AX, bool F, bool I>
+struct OpPMid {
+    static constexpr bool FWD = F, INV = I, FINAL = false;
+    static constexpr int K = 0;
+    static constexpr unsigned MAXMASK = 0;
+    C2<T>* w;
+    Scal* S;
+    struct State {};
+    __device__ bool skip(const Geo&, int b) const { return S[b].done != 0; }
+    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = w[lc.at(q)];
+    }
+    __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
+                             const C2<T>*) const {
+        if constexpr (F && I) {
+            const Scal& s = S[lc.b];
+            double ko;
+            if (AX == 1) {
+                const double xi = freq_of(lc.i1, g.n[0], s.L[0]);
+                ko = xi * xi;
+            } else {
+                const double xi = freq_of(lc.i1, g.n[0], s.L[0]);
+                const double mu = freq_of(lc.i2, g.n[1], s.L[1]);
+                ko = xi * xi + mu * mu;
+            }
+            const double invN = 1.0 / (double)g.N;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double k = freq_of(lc.k(q), lc.M, s.L[AX]);
+                v[q] = scl(v[q], (T)(invN / (s.lamt + 0.5 * (ko + k * k))));
+            }
+        }
+    }
+    __device__ void store(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1]) const {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[lc.at(q)] = v[q];
+    }
+    __device__ void finalize(const Geo&, int, const double*) const {}
+};
+
+// ---------------------------------------------------------------------------------------------
+// Phase A, last pass (x): inverse x, epilogue scaling -> P r, and the CG reductions.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+struct OpPLast {
+    static constexpr bool FWD = false, INV = true, FINAL = true;
+    static constexpr int K = A_K;
+    static constexpr unsigned MAXMASK = A_MAXMASK;
+    IterFields<T> f;
+    Scal* S;
+    int post;
+    struct State {};
+    __device__ bool skip(const Geo&, int b) const { return S[b].done != 0; }
+    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = f.w[lc.at(q)];
+    }
+    __device__ void spectral(const Geo&, const LineCtx&, State&, C2<T> (&)[8], double (&)[K], C2<T>*,
+                             const C2<T>*) const {}
+    __device__ void store(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K]) const {
+        const Scal& s = S[lc.b];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = lc.at(q);
+            const C2<T> ph = f.phi[i];
+            C2<T> pr = v[q];
+            if (post) pr = scl(pr, pscale<T>(post, pv_diag(s, (double)f.V[i], (double)abs2(ph))));
+            f.pr[i] = pr;
+            cg_sums<T>(acc, f.r[i], pr, f.rp[i], f.pp[i], ph);
+        }
+    }
+    __device__ void finalize(const Geo&, int b, const double* t) const { fin_direction(S[b], t); }
+};
+
+// ---------------------------------------------------------------------------------------------
+// Phase B: p = -P r + beta_cg p_{n-1} - rho phi (written over p_{n-1}), phat = p/||p||, and
+// L phat = sum_a F_a^{-1}[sigma_a F_a phat] + V phat.  When omega != 0 the passes along x and y
+// also transform phi (forward only) to accumulate <phi, R phi>, Re<phi, R phat>, <phat, R phat>
+// (Parseval per line), which keeps lambda~ exact without a separate rotation field.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int AX, bool FIRST, bool LAST>
+struct OpLp {
+    static constexpr bool FWD = true, INV = true, FINAL = LAST;
+    static constexpr int K = B_K;
+    static constexpr unsigned MAXMASK = B_MAXMASK;
+    IterFields<T> f;
+    Scal* S;
+    Partials prev0, prev1;  // partials of the earlier B passes (reduced by the last one)
+    struct State {
+        C2<T> ph[8];
+        C2<T> p[8];
+    };
+    __device__ bool skip(const Geo&, int b) const { return S[b].done != 0; }
+    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
+        const Scal& s = S[lc.b];
+        const T inv = (T)(1.0 / s.pnorm);
+        const bool need_phi = LAST || (s.omega != 0.0 && AX < 2);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = lc.at(q);
+            C2<T> p;
+            if constexpr (FIRST) {
+                const C2<T> ph = f.phi[i];
+                p = sub(scl(f.pp[i], (T)s.beta_cg), add(f.pr[i], scl(ph, (T)s.rho)));
+                f.pp[i] = p;
+                st.ph[q] = ph;
+            } else {
+                p = f.pp[i];
+                if (need_phi) st.ph[q] = f.phi[i];
+            }
+            st.p[q] = v[q] = scl(p, inv);
+        }
+    }
+    __device__ void spectral(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K],
+                             C2<T>* buf, const C2<T>* tw) const {
+        const Scal& s = S[lc.b];
+        const double rot = rot_coef_s<AX>(s, lc);
+        const double invM = 1.0 / lc.M;
+        if (AX < 2 && s.omega != 0.0 && s.dim >= 2) {
+            C2<T> u[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[q] = st.ph[q];
+            fft_line<T, -1>(u, buf, tw, lc.t, lc.lg);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double xi = freq_of(lc.k(q), lc.M, s.L[AX]);
+                const double wr = rot * xi * invM;
+                acc[B_CR] += wr * (double)abs2(v[q]);
+                acc[B_AR] += wr * (double)abs2(u[q]);
+                acc[B_BR] += wr * (double)redot(u[q], v[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double xi = freq_of(lc.k(q), lc.M, s.L[AX]);
+            v[q] = scl(v[q], (T)((0.5 * xi * xi + rot * xi) * invM));
+        }
+    }
+    __device__ void store(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K]) const {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = lc.at(q);
+            C2<T> o = v[q];
+            if constexpr (!FIRST) o = add(o, f.w[i]);
+            if constexpr (!LAST) {
+                f.w[i] = o;
+            } else {
+                const C2<T> ph = st.ph[q], p = st.p[q];
+                o = add(o, scl(p, f.V[i]));
+                f.lp[i] = o;
+                // line-search sums (A = |phi|^2, B = Re conj(phi) phat, C = |phat|^2)
+                const double A = abs2(ph), Bq = redot(ph, p), Cq = abs2(p);
+                acc[B_C] += (double)redot(p, o);
+                acc[B_B] += (double)redot(ph, o);
+                acc[B_AA] += A * A;
+                acc[B_AB] += A * Bq;
+                acc[B_ACA] += A * (Cq - A);
+                acc[B_CACA] += (Cq - A) * (Cq - A);
+                acc[B_CAB] += (Cq - A) * Bq;
+                acc[B_BB] += Bq * Bq;
+                acc[B_AC] += A * Cq;
+                acc[B_SB] += Bq;
+                acc[B_SC] += Cq;
+                if (!isfinite((double)o.x) || !isfinite((double)o.y)) acc[B_NF] = 1.0;
+            }
+        }
+    }
+    __device__ void finalize(const Geo&, int b, const double* t) const {
+        __shared__ double tot[B_K];
+        __shared__ double part_out[B_K];
+        __shared__ double scratch[(1024 / 64) * B_K];
+        for (int k = threadIdx.x; k < B_K; k += blockDim.x) tot[k] = t[k];
+        __syncthreads();
+        const Partials* pv[2] = {&prev0, &prev1};
+        for (int q = 0; q < 2; ++q) {
+            const Partials& P = *pv[q];
+            if (!P.parts) continue;
+            reduce_partials<B_K>(P.parts + (size_t)b * P.nb * B_K, P.nb, scratch, part_out, B_MAXMASK);
+            for (int k = threadIdx.x; k < B_K; k += blockDim.x) {
+                const bool mx = (B_MAXMASK >> k) & 1u;
+                tot[k] = mx ? fmax(tot[k], part_out[k]) : tot[k] + part_out[k];
+            }
+            __syncthreads();
+        }
+        fin_step(S[b], tot);
+    }
+};
+
+// ---------------------------------------------------------------------------------------------
+// Phase C: pointwise update with fresh scalars (one kernel, no transforms).
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(IterFields<T> f, Scal* S, int64_t N, int nbpi, Partials pr) {
+    __shared__ double red[(256 / 64 + 1) * C_K + 8];
+    __shared__ int flag;
+    const int b = blockIdx.x / nbpi;
+    const int blk = blockIdx.x - b * nbpi;
+    Scal& s = S[b];
+    if (s.done) return;
+    const T cphi = (T)s.c_phi, cp = (T)s.c_p, cL = (T)s.c_L, cLp = (T)s.c_Lp;
+    double acc[C_K];
+#pragma unroll
+    for (int k = 0; k < C_K; ++k) acc[k] = 0.0;
+    const int64_t chunk = (N + nbpi - 1) / nbpi;
+    const int64_t lo = (int64_t)blk * chunk, hi = min(N, lo + chunk);
+    const int64_t off = (int64_t)b * N;
+    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
+        const int64_t i = off + j;
+        const C2<T> ph = f.phi[i];
+        const C2<T> np = add(scl(ph, cphi), scl(f.pp[i], cp));
+        const C2<T> nl = add(scl(f.Lphi[i], cL), scl(f.lp[i], cLp));
+        f.phi[i] = np;
+        f.Lphi[i] = nl;
+        const double r2 = abs2(np);
+        acc[C_A] += (double)redot(np, nl);
+        acc[C_Q4] += r2 * r2;
+        acc[C_N2] += r2;
+        acc[C_DPHI] = fmax(acc[C_DPHI], sqrt((double)abs2(sub(np, ph))));
+        if (!isfinite(r2)) acc[C_NF] = 1.0;
+    }
+    __shared__ double totals[C_K];
+    block_reduce<C_K>(acc, red, totals, C_MAXMASK);
+    double* P = pr.parts + ((size_t)b * nbpi + blk) * C_K;
+    for (int k = threadIdx.x; k < C_K; k += blockDim.x) P[k] = totals[k];
+    if (last_block(pr.counters + b, (unsigned)nbpi, &flag)) {
+        reduce_partials<C_K>(pr.parts + (size_t)b * nbpi * C_K, nbpi, red, totals, C_MAXMASK);
+        fin_update(s, totals);
+    }
+}
+
+// Diagonal preconditioners (identity, P_V): residual, P r and all phase-A sums in one sweep.
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, Scal* S, int64_t N, int nbpi, int pre,
+                                                   Partials pr) {
+    __shared__ double red[(256 / 64 + 1) * A_K + 8];
+    __shared__ int flag;
+    const int b = blockIdx.x / nbpi;
+    const int blk = blockIdx.x - b * nbpi;
+    Scal& s = S[b];
+    if (s.done) return;
+    double acc[A_K];
+#pragma unroll
+    for (int k = 0; k < A_K; ++k) acc[k] = 0.0;
+    const T lam = (T)s.lam, beta = (T)s.beta;
+    const int64_t chunk = (N + nbpi - 1) / nbpi;
+    const int64_t lo = (int64_t)blk * chunk, hi = min(N, lo + chunk);
+    const int64_t off = (int64_t)b * N;
+    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
+        const int64_t i = off + j;
+        const C2<T> ph = f.phi[i];
+        const T rho = abs2(ph);
+        const C2<T> r = add(f.Lphi[i], scl(ph, beta * rho - lam));
+        f.r[i] = r;
+        const C2<T> pr = scl(r, pscale<T>(pre, pv_diag(s, (double)f.V[i], (double)rho)));
+        f.pr[i] = pr;
+        res_sums<T>(acc, r);
+        cg_sums<T>(acc, r, pr, f.rp[i], f.pp[i], ph);
+    }
+    __shared__ double totals[A_K];
+    block_reduce<A_K>(acc, red, totals, A_MAXMASK);
+    double* P = pr.parts + ((size_t)b * nbpi + blk) * A_K;
+    for (int k = threadIdx.x; k < A_K; k += blockDim.x) P[k] = totals[k];
+    if (last_block(pr.counters + b, (unsigned)nbpi, &flag)) {
+        reduce_partials<A_K>(pr.parts + (size_t)b * nbpi * A_K, nbpi, red, totals, A_MAXMASK);
+        fin_residual(s, totals[A_RES], totals[A_NF]);
+        fin_direction(s, totals);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host: enqueue one iteration for B instances.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
+    const Geo& g = c.g;
+    const bool f64 = sizeof(T) == 8;
+    const int cb = (int)sizeof(C2<T>);
+    const IterFields<T>& f = c.f;
+    hipError_t e;
+    auto parts = [&](int region, int K, int ax) {
+        Partials p;
+        p.parts = c.parts + (size_t)region * c.region_doubles;
+        p.counters = c.counters + (size_t)region * c.B;
+        p.nb = pass_blocks_per_field(g, ax, cb);
+        (void)K;
+        return p;
+    };
+    const Partials none{nullptr, nullptr, 0};
+    // ---- phase A ----
+    int pre = 0, post = 0;
+    const bool spectral_p = c.precond == GPE_P_KINETIC || c.precond == GPE_P_COMBINED || c.precond == GPE_P_C1 ||
+                            c.precond == GPE_P_C2;
+    if (c.precond == GPE_P_COMBINED) pre = post = 1;
+    if (c.precond == GPE_P_C1) post = 2;
+    if (c.precond == GPE_P_C2 || c.precond == GPE_P_POTENTIAL) pre = 2;
+    if (!spectral_p) {
+        // diagonal P (identity or P_V): pointwise residual + P r + reductions in one kernel
+        const int nbpi = c.pointwise_blocks;
+        Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, c.counters + (size_t)R_A1 * c.B, nbpi};
+        hipLaunchKernelGGL(k_resid_diag<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f, c.S, g.N, nbpi, pre,
+                           pr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (g.dim == 1) {
+        OpResid<T, true> op{f, c.S, pre, post};
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, parts(R_A1, A_K, 0), s)) != hipSuccess) return e;
+    } else {
+        OpResid<T, false> op{f, c.S, pre, post};
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, parts(R_A1, A_K, 0), s)) != hipSuccess) return e;
+        if (g.dim == 2) {
+            OpPMid<T, 1, true, true> y{f.w, c.S};
+            if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y, none, s)) != hipSuccess) return e;
+        } else {
+            OpPMid<T, 1, true, false> y1{f.w, c.S};
+            if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y1, none, s)) != hipSuccess) return e;
+            OpPMid<T, 2, true, true> z{f.w, c.S};
+            if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), z, none, s)) != hipSuccess) return e;
+            OpPMid<T, 1, false, true> y2{f.w, c.S};
+            if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y2, none, s)) != hipSuccess) return e;
+        }
+        OpPLast<T> op3{f, c.S, post};
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op3, parts(R_A3, A_K, 0), s)) != hipSuccess) return e;
+    }
+    // ---- phase B ----
+    if (g.dim == 1) {
+        OpLp<T, 0, true, true> op{f, c.S, none, none};
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, parts(R_B0, B_K, 0), s)) != hipSuccess) return e;
+    } else if (g.dim == 2) {
+        OpLp<T, 0, true, false> ox{f, c.S, none, none};
+        Partials p0 = parts(R_B0, B_K, 0);
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, p0, s)) != hipSuccess) return e;
+        OpLp<T, 1, false, true> oy{f, c.S, p0, none};
+        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, parts(R_B1, B_K, 1), s)) != hipSuccess) return e;
+    } else {
+        OpLp<T, 0, true, false> ox{f, c.S, none, none};
+        Partials p0 = parts(R_B0, B_K, 0);
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, p0, s)) != hipSuccess) return e;
+        OpLp<T, 1, false, false> oy{f, c.S, none, none};
+        Partials p1 = parts(R_B1, B_K, 1);
+        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, p1, s)) != hipSuccess) return e;
+        OpLp<T, 2, false, true> oz{f, c.S, p0, p1};
+        if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), oz, parts(R_B2, B_K, 2), s)) != hipSuccess) return e;
+    }
+    // ---- phase C ----
+    {
+        const int nbpi = c.pointwise_blocks;
+        Partials pr{c.parts + (size_t)R_C * c.region_doubles, c.counters + (size_t)R_C * c.B, nbpi};
+        hipLaunchKernelGGL(k_update<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f, c.S, g.N, nbpi, pr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template hipError_t enqueue_iteration<double>(const IterCtx<double>&, hipStream_t);
+template hipError_t enqueue_iteration<float>(const IterCtx<float>&, hipStream_t);
+
+}  // namespace gpe

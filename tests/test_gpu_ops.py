@@ -1,0 +1,147 @@
+"""GPU parity of the operators (H apply, energy, preconditioners) against the FP64 oracle, through
+the C ABI, on seeded inputs: shapes cover every supported dimension, anisotropic grids, several
+lines per workgroup and the smallest/largest transform sizes."""
+import math
+
+import numpy as np
+import pytest
+
+from gpe_inputs import Problem, harmonic_potential, random_field
+from oracle import gpe_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    (1, (8,), (2.0,)),
+    (1, (256,), (16.0,)),
+    (1, (1024,), (20.0,)),
+    (2, (8, 8), (3.0, 3.0)),
+    (2, (16, 64), (4.0, 6.0)),
+    (2, (64, 16), (6.0, 4.0)),
+    (2, (8, 1024), (2.0, 12.0)),
+    (2, (1024, 8), (12.0, 2.0)),
+    (2, (256, 256), (16.0, 16.0)),
+    (2, (512, 512), (16.0, 16.0)),
+    (3, (8, 8, 8), (3.0, 3.0, 3.0)),
+    (3, (16, 32, 8), (4.0, 5.0, 3.0)),
+    (3, (64, 64, 64), (8.0, 8.0, 8.0)),
+]
+IDS = ["x".join(map(str, s[1])) for s in SHAPES]
+TOL = {"f64": 2e-12, "f32": 2e-5}
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1611_02045_amd import gpe  # noqa: F401  (fails loudly if the library is missing)
+    gpe.lib()
+    return torch
+
+
+def _setup(dim, n, L, beta=300.0, omega=0.7, seed=5):
+    prob = Problem(dim, n, L, beta, omega if dim > 1 else 0.0)
+    V = harmonic_potential(prob, (1.0, 1.3, 0.8))
+    phi = random_field(prob, seed, envelope=0.5 / max(L) ** 2)
+    return prob, V, phi
+
+
+def _to(torch, x, dtype):
+    real = {"f64": torch.float64, "f32": torch.float32}[dtype]
+    cplx = {"f64": torch.complex128, "f32": torch.complex64}[dtype]
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    return t.to(device="cuda", dtype=cplx if np.iscomplexobj(x) else real)
+
+
+def _relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dim,n,L", SHAPES, ids=IDS)
+def test_apply_H_matches_oracle(torch_gpu, dim, n, L, dtype):
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, phi = _setup(dim, n, L)
+    print(f"apply_H {dim}D n={n} {dtype}", flush=True)
+    ref = O.hamiltonian(prob, V, phi)
+    plan = gpe.Plan.from_problem(prob, dtype)
+    out = plan.apply_H(_to(torch, phi, dtype), _to(torch, V, dtype)).cpu().numpy()
+    assert _relerr(out, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dim,n,L", SHAPES, ids=IDS)
+def test_energy_matches_oracle(torch_gpu, dim, n, L, dtype):
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, phi = _setup(dim, n, L)
+    print(f"energy {dim}D n={n} {dtype}", flush=True)
+    ref = O.energy_parts(prob, V, phi)
+    plan = gpe.Plan.from_problem(prob, dtype)
+    E, parts = plan.energy(_to(torch, phi, dtype), _to(torch, V, dtype), parts=True)
+    scale = abs(ref.kinetic) + abs(ref.potential) + abs(ref.interaction) + abs(ref.rotation)
+    assert abs(E - ref.total) < TOL[dtype] * scale
+    for key, val in (("kinetic", ref.kinetic), ("potential", ref.potential), ("interaction", ref.interaction),
+                     ("rotation", ref.rotation)):
+        assert abs(parts[key] - val) < TOL[dtype] * scale, key
+
+
+@pytest.mark.parametrize("kind", ["none", "kinetic", "potential", "combined", "c1", "c2"])
+@pytest.mark.parametrize("dim,n,L", [SHAPES[1], SHAPES[4], SHAPES[8], SHAPES[11]], ids=["1d", "2d-aniso", "2d", "3d"])
+def test_preconditioners_match_oracle(torch_gpu, dim, n, L, kind):
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, phi = _setup(dim, n, L)
+    r = random_field(prob, 77)
+    print(f"precond {kind} {dim}D n={n}", flush=True)
+    plan = gpe.Plan.from_problem(prob, "f64")
+    P, Vg, R = _to(torch, phi, "f64"), _to(torch, V, "f64"), _to(torch, r, "f64")
+    # adaptive shift lambda~ computed on the device
+    ref = O.apply_preconditioner(prob, kind, V, phi, r)
+    out = plan.precond(kind, P, Vg, R).cpu().numpy()
+    assert _relerr(out, ref) < 1e-12
+    # explicit shift
+    ref = O.apply_preconditioner(prob, kind, V, phi, r, alpha=2.5)
+    out = plan.precond(kind, P, Vg, R, alpha=2.5).cpu().numpy()
+    assert _relerr(out, ref) < 1e-12
+
+
+def test_preconditioner_rejects_non_spd(torch_gpu):
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, phi = _setup(2, (16, 16), (4.0, 4.0))
+    plan = gpe.Plan.from_problem(prob, "f64")
+    with pytest.raises(gpe.GpeError) as ei:
+        plan.precond("combined", _to(torch, phi, "f64"), _to(torch, V - 1e3, "f64"), _to(torch, phi, "f64"), alpha=1.0)
+    assert ei.value.status == -1
+    with pytest.raises(gpe.GpeError):
+        plan.precond("kinetic", _to(torch, phi, "f64"), _to(torch, V, "f64"), _to(torch, phi, "f64"), alpha=-1.0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_apply_H_batched(torch_gpu, dtype):
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, _ = _setup(2, (128, 64), (10.0, 8.0))
+    phis = np.stack([random_field(prob, s, envelope=0.01) for s in range(5)])
+    plan = gpe.Plan.from_problem(prob, dtype)
+    out = plan.apply_H_batched(_to(torch, phis, dtype), _to(torch, V, dtype)).cpu().numpy()
+    for b in range(5):
+        assert _relerr(out[b], O.hamiltonian(prob, V, phis[b])) < TOL[dtype]
+
+
+def test_energy_grad(torch_gpu):
+    """grad_phi = 2 h^d H phi, grad_V = h^d |phi|^2, dE/dbeta, dE/domega against the oracle."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, phi = _setup(2, (64, 32), (6.0, 5.0))
+    plan = gpe.Plan.from_problem(prob, "f64")
+    gphi, gV, db, do = plan.energy_grad(_to(torch, phi, "f64"), _to(torch, V, "f64"))
+    w = O.cell(prob)
+    assert _relerr(gphi.cpu().numpy(), 2 * w * O.hamiltonian(prob, V, phi)) < 1e-12
+    assert _relerr(gV.cpu().numpy(), w * np.abs(phi) ** 2) < 1e-14
+    assert abs(db - 0.5 * w * np.sum(np.abs(phi) ** 4)) < 1e-12 * abs(db)
+    lz = O.inner(prob, phi, O.angular_momentum(prob, phi)).real
+    assert abs(do + lz) < 1e-12 * max(1.0, abs(lz))

@@ -1,0 +1,159 @@
+"""GPU parity of the PG / PCG solver against the FP64 oracle through the C ABI.
+
+Same seeded inputs on both sides; the GPU path's per-iteration record (energy, chemical potential,
+residual, step) is compared with the oracle's for the first iterations, the final state is
+compared in energy (1e-10 relative in FP64 mode, 1e-6 in mixed mode) and density, and the
+closed-form ground state (beta = 0: E = d/2) pins the end-to-end path."""
+import math
+
+import numpy as np
+import pytest
+
+from gpe_inputs import (Problem, gaussian, harmonic_potential, noisy_gaussian_1d, paper_initial, random_field,
+                        vortex_seed_2d)
+from oracle import gpe_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1611_02045_amd import gpe
+    gpe.lib()
+    return torch
+
+
+def _dev(torch, x, f64=True):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if np.iscomplexobj(x):
+        return t.to("cuda", torch.complex128 if f64 else torch.complex64)
+    return t.to("cuda", torch.float64 if f64 else torch.float32)
+
+
+def _gpu_solve(torch, prob, V, phi0, dtype="f64", **opts):
+    from paper_1611_02045_amd import gpe
+    plan = gpe.Plan.from_problem(prob, dtype)
+    phi = _dev(torch, phi0, dtype == "f64")
+    rep = plan.pcg_solve(_dev(torch, V, dtype == "f64"), phi, **opts)
+    hist = plan.history() if opts.get("record_history") else None
+    return rep, phi.cpu().numpy().astype(np.complex128), hist
+
+
+CASES = {
+    "1d": (Problem(1, (256,), (16.0,), 250.0, 0.0), "1d"),
+    "2d": (Problem(2, (64, 64), (8.0, 8.0), 100.0, 0.5), "2d"),
+    "2d-aniso": (Problem(2, (64, 32), (8.0, 6.0), 60.0, 0.3), "2d"),
+    "3d": (Problem(3, (16, 16, 16), (5.0, 5.0, 5.0), 40.0, 0.4), "3d"),
+}
+
+
+def _inputs(key):
+    prob, kind = CASES[key]
+    V = harmonic_potential(prob)
+    if kind == "1d":
+        phi0 = noisy_gaussian_1d(prob)
+    elif kind == "2d":
+        phi0 = vortex_seed_2d(prob, 7)
+    else:
+        phi0 = random_field(prob, 9, envelope=0.1)
+    return prob, V, phi0
+
+
+@pytest.mark.parametrize("key", list(CASES))
+def test_trajectory_matches_oracle(torch_gpu, key):
+    """First iterations: E_n, lambda_n, ||r_n||_inf and the accepted step agree with the oracle."""
+    prob, V, phi0 = _inputs(key)
+    print(f"trajectory {key}", flush=True)
+    ref = O.pcg(prob, V, phi0, tol_res=1e-30, max_iter=12, record=True)
+    rep, _, hist = _gpu_solve(torch_gpu, prob, V, phi0, tol_res=1e-30, max_iter=12, record_history=1,
+                              check_every=4)
+    assert rep["iters"] == 12 and rep["status"] == 1
+    for h_ref, h in zip(ref.history, hist):
+        assert int(h["n"]) == h_ref["n"]
+        assert abs(h["E"] - h_ref["E"]) < 1e-11 * abs(h_ref["E"])
+        assert abs(h["lam"] - h_ref["lam"]) < 1e-11 * abs(h_ref["lam"])
+        assert abs(h["res"] - h_ref["res"]) < 1e-8 * h_ref["res"] + 1e-13
+        if "theta" in h_ref:
+            assert abs(h["theta"] - h_ref["theta"]) < 1e-7 * h_ref["theta"]
+            assert int(h["restarted"]) == int(h_ref["restarted"])
+
+
+@pytest.mark.parametrize("key", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_converged_state_matches_oracle(torch_gpu, key, precision):
+    prob, V, phi0 = _inputs(key)
+    tol = 1e-9
+    print(f"solve {key} {precision}", flush=True)
+    ref = O.pcg(prob, V, phi0, tol_res=tol, max_iter=3000)
+    rep, phi, _ = _gpu_solve(torch_gpu, prob, V, phi0, tol_res=tol, max_iter=3000, precision=precision)
+    assert ref.status == "converged"
+    assert rep["status"] == 0, rep
+    assert rep["res_inf"] <= tol
+    rel = 1e-10 if precision == "fp64" else 1e-6
+    assert abs(rep["E"] - ref.E) < rel * abs(ref.E)
+    # the oracle's own evaluation of the GPU state
+    assert abs(O.energy(prob, V, phi) - ref.E) < rel * abs(ref.E)
+    gap = float(np.max(np.abs(np.abs(phi) ** 2 - np.abs(ref.phi) ** 2)))
+    print(f"  iters gpu={rep['iters']} oracle={ref.iters} density Linf gap={gap:.3e}")
+    assert gap < 1e-6
+
+
+@pytest.mark.parametrize("method,precond", [("pg", "combined"), ("pcg", "kinetic"), ("pcg", "potential"),
+                                            ("pcg", "none"), ("pcg", "c1"), ("pcg", "c2")])
+def test_methods_and_preconditioners(torch_gpu, method, precond):
+    prob, V, phi0 = _inputs("2d")
+    print(f"method {method} {precond}", flush=True)
+    ref = O.pcg(prob, V, phi0, method=method, precond=precond, tol_res=1e-30, max_iter=8, record=True)
+    rep, _, hist = _gpu_solve(torch_gpu, prob, V, phi0, method=method, precond=precond, tol_res=1e-30,
+                              max_iter=8, record_history=1)
+    for h_ref, h in zip(ref.history, hist):
+        assert abs(h["E"] - h_ref["E"]) < 1e-11 * abs(h_ref["E"])
+        assert abs(h["res"] - h_ref["res"]) < 1e-8 * h_ref["res"]
+
+
+def test_beta0_gives_exact_ground_state(torch_gpu):
+    """1-D harmonic trap, beta = 0, seeded noisy start: E = 1/2 to 1e-10."""
+    prob = Problem(1, (256,), (16.0,), 0.0, 0.0)
+    V = harmonic_potential(prob)
+    rep, phi, _ = _gpu_solve(torch_gpu, prob, V, noisy_gaussian_1d(prob), tol_res=1e-10)
+    assert rep["status"] == 0
+    assert abs(rep["E"] - 0.5) < 1e-10
+    g = gaussian(prob)
+    ov = abs(O.inner(prob, g, phi))
+    assert abs(ov - 1.0) < 1e-10
+
+
+def test_2d_beta0_rotating_ground_state(torch_gpu):
+    """2-D harmonic trap, beta = 0, Omega = 0.6: the minimum is E = 1 (m = 0 Gaussian)."""
+    prob = Problem(2, (64, 64), (8.0, 8.0), 0.0, 0.6)
+    V = harmonic_potential(prob)
+    rep, _, _ = _gpu_solve(torch_gpu, prob, V, random_field(prob, 3, envelope=0.05), tol_res=1e-10)
+    assert rep["status"] == 0 and abs(rep["E"] - 1.0) < 1e-10
+
+
+def test_paper_sector_energy(torch_gpu):
+    """Start (b) at Omega = 0.5, beta = 500 on 256^2: the printed 8.2606 = 8.7606 - Omega."""
+    prob = Problem(2, (256, 256), (16.0, 16.0), 500.0, 0.5)
+    V = harmonic_potential(prob)
+    rep, _, _ = _gpu_solve(torch_gpu, prob, V, paper_initial(prob, "b", 0.5), tol_res=1e-7)
+    assert rep["status"] == 0
+    assert abs(rep["E"] - 8.2606) < 6e-5
+
+
+def test_max_iter_reports_not_converged(torch_gpu):
+    prob, V, phi0 = _inputs("2d")
+    rep, _, _ = _gpu_solve(torch_gpu, prob, V, phi0, tol_res=1e-14, max_iter=5)
+    assert rep["status"] == 1 and rep["iters"] == 5
+
+
+def test_nonfinite_input_is_reported(torch_gpu):
+    from paper_1611_02045_amd import gpe
+    prob, V, phi0 = _inputs("2d")
+    phi0 = phi0.copy()
+    phi0[3, 5] = np.nan
+    with pytest.raises(gpe.GpeError) as ei:
+        _gpu_solve(torch_gpu, prob, V, phi0)
+    assert ei.value.status == -4
