@@ -168,6 +168,16 @@ int gpe_energy_grad(gpe_plan_t* plan, const void* phi, const void* V, void* grad
 int gpe_adjoint_solve(gpe_plan_t* plan, const void* phi_star, const void* V, const void* rhs,
                       void* mu, const gpe_pcg_opts_t* opts, gpe_pcg_report_t* report, void* stream);
 
+/* Instrumented run for measurement: `iters` solver iterations at the precision of
+ * opts->precision (0: FP64 fields, 1: FP32 fields; an FP32 plan always uses FP32) from phi
+ * (device, left unchanged), with every kernel launch of an iteration bracketed by HIP events
+ * on `stream`.  Host outputs, `cap` entries each: avg_ms[k] = mean event-to-event time of the
+ * k-th kernel of the iteration, bytes[k] = its algorithmic HBM bytes per launch (fields read
+ * and written once), names = cap rows of 32 chars.  Returns the number of kernels per
+ * iteration (>= 0) or an error.  The convergence test is disabled during the run. */
+int gpe_pcg_profile(gpe_plan_t* plan, const void* V, const void* phi, const gpe_pcg_opts_t* opts, int iters,
+                    int cap, double* avg_ms, double* bytes, char* names, void* stream);
+
 /* Message of the last error on this thread ("" if none). */
 const char* gpe_last_error(void);
 

@@ -183,6 +183,72 @@ int gpe_pcg_history(gpe_plan_t* plan, double* hist, int cap) {
     return (int)rows;
 }
 
+int gpe_pcg_profile(gpe_plan_t* plan, const void* V, const void* phi, const gpe_pcg_opts_t* opts, int iters, int cap,
+                    double* avg_ms, double* bytes, char* names, void* stream) {
+    if (!plan || !V || !phi || !avg_ms || !bytes || !names) { set_error("NULL argument"); return GPE_EINVAL; }
+    int st = validate_opts(opts);
+    if (st != GPE_OK) return st;
+    if (iters < 1 || cap < 1) { set_error("iters and cap must be >= 1"); return GPE_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    const Geo& g = plan->g;
+    const int64_t N = g.N;
+    HIPCHK(reduce_init(plan->red, 1, R_COUNT, std::max<size_t>(1 << 18, R_COUNT * region_doubles_for(g, 1))));
+    HIPCHK(plan->scal.ensure(sizeof(Scal)));
+    gpe_pcg_opts_t o = *opts;
+    o.tol_res_inf = 0.0;
+    o.tol_energy = 0.0;
+    o.max_iter = (int64_t)iters + 1000;
+    std::vector<Scal> hs(1, make_scal(plan->prob, g, o));
+    PhaseArgs pa;
+    pa.g = g;
+    pa.B = 1;
+    pa.tw = &plan->tw;
+    pa.S = (Scal*)plan->scal.ptr;
+    pa.red = &plan->red;
+    pa.region_doubles = region_doubles_for(g, 1);
+    pa.precond = o.precond;
+    pa.check_every = 1;
+    pa.refresh_every = 0;
+    pa.final_f_r_is_rp = false;
+    KernelTimer timer;
+    hipError_t e = timer.init();
+    const bool fp32 = !plan->f64() || o.precision == 1;
+    if (e == hipSuccess) {
+        if (fp32) {
+            IterFields<float> f = carve_fields<float>(plan->f64() ? plan->solver32 : plan->solver, N, &e);
+            if (e == hipSuccess) {
+                if (plan->f64()) {
+                    e = convert_complex(false, phi, f.phi, N, s);
+                    if (e == hipSuccess) e = convert_real(false, V, f.V, N, s);
+                } else {
+                    e = copy_bytes(phi, f.phi, sizeof(float) * 2 * N, s);
+                    if (e == hipSuccess) e = copy_bytes(V, f.V, sizeof(float) * N, s);
+                }
+            }
+            if (e == hipSuccess) e = profile_phase<float>(pa, f, hs, iters, timer, s);
+        } else {
+            IterFields<double> f = carve_fields<double>(plan->solver, N, &e);
+            if (e == hipSuccess) e = copy_bytes(phi, f.phi, sizeof(double) * 2 * N, s);
+            if (e == hipSuccess) e = copy_bytes(V, f.V, sizeof(double) * N, s);
+            if (e == hipSuccess) e = profile_phase<double>(pa, f, hs, iters, timer, s);
+        }
+    }
+    int n = 0;
+    if (e == hipSuccess) {
+        n = std::min(timer.slots, cap);
+        for (int k = 0; k < n; ++k) {
+            avg_ms[k] = timer.launches[k] ? timer.total_ms[k] / (double)timer.launches[k] : 0.0;
+            bytes[k] = timer.bytes[k];
+            std::memset(names + 32 * k, 0, 32);
+            std::strncpy(names + 32 * k, timer.names[k] ? timer.names[k] : "?", 31);
+        }
+    }
+    timer.destroy();
+    HIPCHK(e);
+    if (hs[0].done) { set_error("the instrumented iteration finished early (non-finite or line search)"); return GPE_ENONFINITE; }
+    return n;
+}
+
 int gpe_pcg_solve_batched(int, const gpe_problem_t*, int, void* const*, void* const*, const gpe_pcg_opts_t*,
                           gpe_pcg_report_t*, void*) {
     set_error("gpe_pcg_solve_batched: not implemented yet");

@@ -91,7 +91,7 @@ struct Scal {
     double best_res;
     int64_t best_n;
     double switch_res;
-    int32_t stall_window, pad0;
+    int32_t stall_window, has_step;   // has_step: a retraction step is pending (applied by phase A)
     // history
     double* hist;      // device ring of rows of 8 doubles, nullable
     int64_t hist_cap;

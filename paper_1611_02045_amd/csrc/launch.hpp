@@ -8,6 +8,9 @@
 namespace gpe {
 
 constexpr size_t kPassLdsBudget = 96 * 1024;
+// Workgroup size cap of the passes: 512 threads lets every kernel keep up to 256 VGPRs per lane
+// (no scratch spills); x passes use at most 256 threads.
+constexpr int kMaxPassThreads = 512;
 
 inline size_t pass_lds_bytes_cb(int cb, int M, int C, int threads, int K) {
     size_t b = (size_t)cb * ((size_t)M + (size_t)C * line_stride(M));
@@ -16,19 +19,24 @@ inline size_t pass_lds_bytes_cb(int cb, int M, int C, int threads, int K) {
     return b;
 }
 
-// Lines per workgroup for a pass along AX: x-passes pack 256 threads of whole lines; strided
-// passes take enough adjacent lines that each row segment is 128 bytes (coalesced), capped by
-// the 1024-thread workgroup limit and by n_x.
-inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes) {
+// Lines per workgroup for a pass along AX over B instances.  x passes pack up to 256 threads of
+// whole lines; strided passes take enough adjacent lines for 128-byte row segments, capped by
+// the thread and LDS budgets and by n_x.  When the whole launch would have few workgroups (small
+// single grids) the groups are made smaller so that every CU gets work: these launches are bound
+// by latency, not bandwidth.
+inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes, int B = 1) {
     const int TPL = g.n[AX] / 8;
     const int64_t lpf = lines_per_field(g, AX);
+    const int64_t lines = lpf * (int64_t)B;
     int C;
     if (AX == 0) {
         C = std::max(1, 256 / TPL);
+        while (C > 1 && lines / C < 1024) C >>= 1;
     } else {
         C = std::max(1, 128 / complex_bytes);
-        C = std::min(C, std::max(1, 1024 / TPL));
+        C = std::min(C, std::max(1, kMaxPassThreads / TPL));
         C = std::min(C, g.n[0]);
+        while (C > 2 && lines / C < 512) C >>= 1;
     }
     while (C > 1 && (lpf % C) != 0) C >>= 1;
     // keep the LDS footprint (twiddles + lines + reduction scratch) within budget
@@ -36,27 +44,28 @@ inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes) {
     return C;
 }
 
-inline int pass_blocks_per_field(const Geo& g, int AX, int complex_bytes) {
-    return (int)(lines_per_field(g, AX) / pass_lines_per_block(g, AX, complex_bytes));
+inline int pass_blocks_per_field(const Geo& g, int AX, int complex_bytes, int B = 1) {
+    return (int)(lines_per_field(g, AX) / pass_lines_per_block(g, AX, complex_bytes, B));
 }
 
 // Launch one pass over B instances.  `pr` receives nb (blocks per instance) if the Op reduces.
 template <typename T, int AX, class Op>
 hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partials pr, hipStream_t s) {
     const int cb = (int)sizeof(C2<T>);
-    const int C = pass_lines_per_block(g, AX, cb);
+    const int C = pass_lines_per_block(g, AX, cb, B);
     const int TPL = g.n[AX] / 8;
     const int threads = C * TPL;
     const int nb = (int)(lines_per_field(g, AX) / C);
     pr.nb = nb;
     const size_t lds = pass_lds_bytes<T>(g.n[AX], C, threads, Op::K);
-    auto kern = pass_kernel<T, AX, Op>;
+    auto kern = threads <= 256 ? pass_kernel<T, AX, Op, 256> : pass_kernel<T, AX, Op, kMaxPassThreads>;
     static bool attr_set = false;  // one attribute call per instantiation
     if (!attr_set) {
         // Raise the dynamic-LDS cap once; a runtime that does not need it may refuse harmlessly.
-        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPassLdsBudget) !=
-            hipSuccess)
-            (void)hipGetLastError();
+        for (auto k : {pass_kernel<T, AX, Op, 256>, pass_kernel<T, AX, Op, kMaxPassThreads>})
+            if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPassLdsBudget) !=
+                hipSuccess)
+                (void)hipGetLastError();
         attr_set = true;
     }
     hipLaunchKernelGGL(kern, dim3((unsigned)(nb * (int64_t)B)), dim3(threads), lds, s, g, C,

@@ -119,8 +119,8 @@ __device__ __forceinline__ void reduce_partials(const double* parts, int nb, dou
 //   __device__ void store(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
 //   __device__ void finalize(const Geo&, int b, const double* totals) const;   // if FINAL
 // K sums are accumulated per thread in FP64 and reduced deterministically.
-template <typename T, int AX, class Op>
-__global__ __launch_bounds__(1024) void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op,
+template <typename T, int AX, class Op, int MAXT>
+__global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op,
                                                     Partials pr) {
     extern __shared__ double4 smem_raw[];
     const LineCtx lc = decode_line<AX>(g, C);

@@ -7,13 +7,17 @@
 //        1/(lambda~ + |k|^2/2)]  [x pass: inverse x + P_V^{1/2} epilogue + CG reductions]
 //   B  p = -P r + beta_cg p_{n-1} - Re<d, phi> phi, phat = p/||p||, L phat  (Section 5.2)
 //        [x pass, y/z passes; the last one also forms every line-search sum]
-//   C  phi <- (cos t phi + sin t phat)/nu,  L phi <- (cos t L phi + sin t L phat)/nu  (linearity
-//        of L: no transform of phi_{n+1} is needed), fresh <phi, L phi>, sum|phi|^4, ||phi||^2.
+//   The retraction phi <- (cos t phi + sin t phat)/nu, L phi <- (cos t L phi + sin t L phat)/nu
+//        (linearity of L: no transform of phi_{n+1} is needed) is applied pointwise at the start
+//        of the next iteration's phase A, which also reduces the fresh <phi, L phi>, sum|phi|^4
+//        and ||phi||^2 of the new iterate.
 //
 // Scalar logic runs in the last workgroup of each reducing kernel (FP64, deterministic order):
-// the convergence test after A's first pass, beta_cg and the descent test after A, the step
-// after B, and the new lambda / lambda~ / E after C.  Every kernel returns at once for
-// instances whose `done` flag is set, so surplus iterations queued after convergence are no-ops.
+// the convergence test after A's first pass, beta_cg and the descent test after A, and the step
+// after B.  lambda, lambda~ and E of the next iterate follow exactly from the line-search sums
+// (they are quadratic and quartic forms in (cos t, sin t)), so the residual of iteration n+1 can
+// be formed in the same pass that applies the step.  Every kernel returns at once for instances
+// whose `done` flag is set, so surplus iterations queued after convergence are no-ops.
 //
 // Line search: E(cos t phi + sin t phat) - E(phi) is a trigonometric polynomial in t whose
 // coefficients are the reductions <phat, L phat>, <phi, L phat>, <phi, L phi> and sums of
@@ -53,8 +57,16 @@ __device__ __forceinline__ void hist_row(Scal& S, int col, double v) {
 }
 
 // Convergence test at the top of iteration n (Section 5.3; reading: ||r_n||_inf <= tol).
-__device__ void fin_residual(Scal& S, double res, double nonfinite) {
+__device__ void fin_residual(Scal& S, const double* t) {
     if (threadIdx.x == 0) {
+        const double res = t[A_RES], nonfinite = t[A_NF];
+        // fresh scalars of phi_n (the step of the previous iteration has just been applied)
+        S.a = S.cell * t[A_A];
+        S.q4 = S.cell * t[A_Q4];
+        S.nrm2 = S.cell * t[A_N2];
+        S.dphi = t[A_DPHI];
+        S.E = S.a + 0.5 * S.beta * S.q4;
+        S.has_step = 0;
         S.res = res;
         hist_row(S, 0, (double)S.n);
         hist_row(S, 1, S.E);
@@ -129,11 +141,12 @@ __device__ void fin_direction(Scal& S, const double* t) {
 }
 
 // Energy change along the great circle, from the B-phase sums (see the file comment).
+// q0..q4 = sum A B, sum A (C - A), sum B^2, sum (C - A) B, sum (C - A)^2 (times h^d).
 __device__ __forceinline__ double delta_energy(double c, double s, double a, double b, double cc, double beta,
-                                               const double* q) {
+                                               double q0, double q1, double q2, double q3, double q4) {
     const double quad = s * s * (cc - a) + 2.0 * c * s * b;
-    const double quart = 4.0 * c * s * q[0] + 2.0 * s * s * q[1] + 4.0 * c * c * s * s * q[2] +
-                         4.0 * c * s * s * s * q[3] + s * s * s * s * q[4];
+    const double quart = 4.0 * c * s * q0 + 2.0 * s * s * q1 + 4.0 * c * c * s * s * q2 + 4.0 * c * s * s * s * q3 +
+                         s * s * s * s * q4;
     return quad + 0.5 * beta * quart;
 }
 
@@ -153,13 +166,12 @@ __device__ void fin_step(Scal& S, const double* t) {
         const double d2 = 2.0 * (cc + beta * SAC + 2.0 * beta * SBB - S.lam);
         double th = d2 > 0.0 ? -d1 / d2 : S.theta_default;
         th = fmin(fmax(th, 0.0), 1.5707963267948966);
-        const double q[5] = {SAB, SACA, SBB, SCAB, SCACA};
         double acc_t = -1.0, dE = 0.0;
         int j = 0;
         for (; j <= S.max_halvings; ++j) {
             const double tj = th * ldexp(1.0, -j);
             if (!(tj > 0.0)) break;
-            const double e = delta_energy(cos(tj), sin(tj), S.a, b, cc, beta, q);
+            const double e = delta_energy(cos(tj), sin(tj), S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
             if (e < 0.0) {
                 acc_t = tj;
                 dE = e;
@@ -195,35 +207,23 @@ __device__ void fin_step(Scal& S, const double* t) {
             S.aR_next = nu * nu * (c * c * aR + 2.0 * c * s * bR + s * s * cR);
             hist_row(S, 4, acc_t);
             hist_row(S, 6, (double)j);
-        }
-        (void)SAA;
-    }
-    __syncthreads();
-}
-
-// New scalars of phi_{n+1} after the update (Section 2: lambda = <H phi, phi>, E; Section 5.5:
-// lambda~ = <phi, (T + V) phi> + beta h^d sum |phi|^4).
-__device__ void fin_update(Scal& S, const double* t) {
-    if (threadIdx.x == 0 && !S.done) {
-        const double w = S.cell;
-        const double a = w * t[C_A], q4 = w * t[C_Q4], n2 = w * t[C_N2];
-        S.a = a;
-        S.q4 = q4;
-        S.nrm2 = n2;
-        S.dphi = t[C_DPHI];
-        S.aR = S.aR_next;
-        S.lam = a + S.beta * q4;
-        S.lamt = a - S.aR + S.beta * q4;
-        S.E_prev = S.E;
-        S.E = a + 0.5 * S.beta * q4;
-        S.rPr_prev = S.rPr_cur;
-        S.have_prev = 1;
-        S.n += 1;
-        if (S.precision == 1) S.iters_fp32 += 1;
-        if (t[C_NF] > 0.0 || !isfinite(S.E)) {
-            S.status = ST_NONFINITE;
-            S.nonfinite = 1;
-            S.done = 1;
+            // scalars of phi_{n+1} = nu (c phi + s phat), exact in (c, s):
+            //   <phi', L phi'> = nu^2 (c^2 a + 2 c s b + s^2 <phat, L phat>)
+            //   h^d sum|phi'|^4 = nu^4 (sum|phi|^4 + the quartic change of the line search)
+            const double a1 = nu * nu * (c * c * S.a + 2.0 * c * s * b + s * s * cc);
+            const double dq = 4.0 * c * s * SAB + 2.0 * s * s * SACA + 4.0 * c * c * s * s * SBB +
+                              4.0 * c * s * s * s * SCAB + s * s * s * s * SCACA;
+            const double q41 = nu * nu * nu * nu * (SAA + dq);
+            S.E_prev = S.E;
+            S.aR = S.aR_next;
+            S.lam = a1 + beta * q41;
+            S.lamt = a1 - S.aR + beta * q41;
+            S.E = a1 + 0.5 * beta * q41;
+            S.rPr_prev = S.rPr_cur;
+            S.have_prev = 1;
+            S.has_step = 1;
+            S.n += 1;
+            if (S.precision == 1) S.iters_fp32 += 1;
         }
     }
     __syncthreads();
@@ -254,8 +254,9 @@ struct OpResid {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
-            const C2<T> ph = f.phi[i];
-            const C2<T> lp = f.Lphi[i];
+            C2<T> ph = f.phi[i];
+            C2<T> lp = f.Lphi[i];
+            apply_step<T>(f, s, i, ph, lp, acc);
             const T V = f.V[i];
             const T rho = abs2(ph);
             const C2<T> r = add(lp, scl(ph, beta * rho - lam));
@@ -298,7 +299,7 @@ struct OpResid {
         }
     }
     __device__ void finalize(const Geo&, int b, const double* t) const {
-        fin_residual(S[b], t[A_RES], t[A_NF]);
+        fin_residual(S[b], t);
         if constexpr (ONE) fin_direction(S[b], t);
     }
 };
@@ -478,65 +479,23 @@ struct OpLp {
     __device__ void finalize(const Geo&, int b, const double* t) const {
         __shared__ double tot[B_K];
         __shared__ double part_out[B_K];
-        __shared__ double scratch[(1024 / 64) * B_K];
+        __shared__ double scratch[(512 / 64) * B_K];
         for (int k = threadIdx.x; k < B_K; k += blockDim.x) tot[k] = t[k];
         __syncthreads();
-        const Partials* pv[2] = {&prev0, &prev1};
-        for (int q = 0; q < 2; ++q) {
-            const Partials& P = *pv[q];
-            if (!P.parts) continue;
+        auto merge = [&](const Partials P) {
+            if (!P.parts) return;
             reduce_partials<B_K>(P.parts + (size_t)b * P.nb * B_K, P.nb, scratch, part_out, B_MAXMASK);
             for (int k = threadIdx.x; k < B_K; k += blockDim.x) {
                 const bool mx = (B_MAXMASK >> k) & 1u;
                 tot[k] = mx ? fmax(tot[k], part_out[k]) : tot[k] + part_out[k];
             }
             __syncthreads();
-        }
+        };
+        merge(prev0);
+        merge(prev1);
         fin_step(S[b], tot);
     }
 };
-
-// ---------------------------------------------------------------------------------------------
-// Phase C: pointwise update with fresh scalars (one kernel, no transforms).
-// ---------------------------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_update(IterFields<T> f, Scal* S, int64_t N, int nbpi, Partials pr) {
-    __shared__ double red[(256 / 64 + 1) * C_K + 8];
-    __shared__ int flag;
-    const int b = blockIdx.x / nbpi;
-    const int blk = blockIdx.x - b * nbpi;
-    Scal& s = S[b];
-    if (s.done) return;
-    const T cphi = (T)s.c_phi, cp = (T)s.c_p, cL = (T)s.c_L, cLp = (T)s.c_Lp;
-    double acc[C_K];
-#pragma unroll
-    for (int k = 0; k < C_K; ++k) acc[k] = 0.0;
-    const int64_t chunk = (N + nbpi - 1) / nbpi;
-    const int64_t lo = (int64_t)blk * chunk, hi = min(N, lo + chunk);
-    const int64_t off = (int64_t)b * N;
-    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
-        const int64_t i = off + j;
-        const C2<T> ph = f.phi[i];
-        const C2<T> np = add(scl(ph, cphi), scl(f.pp[i], cp));
-        const C2<T> nl = add(scl(f.Lphi[i], cL), scl(f.lp[i], cLp));
-        f.phi[i] = np;
-        f.Lphi[i] = nl;
-        const double r2 = abs2(np);
-        acc[C_A] += (double)redot(np, nl);
-        acc[C_Q4] += r2 * r2;
-        acc[C_N2] += r2;
-        acc[C_DPHI] = fmax(acc[C_DPHI], sqrt((double)abs2(sub(np, ph))));
-        if (!isfinite(r2)) acc[C_NF] = 1.0;
-    }
-    __shared__ double totals[C_K];
-    block_reduce<C_K>(acc, red, totals, C_MAXMASK);
-    double* P = pr.parts + ((size_t)b * nbpi + blk) * C_K;
-    for (int k = threadIdx.x; k < C_K; k += blockDim.x) P[k] = totals[k];
-    if (last_block(pr.counters + b, (unsigned)nbpi, &flag)) {
-        reduce_partials<C_K>(pr.parts + (size_t)b * nbpi * C_K, nbpi, red, totals, C_MAXMASK);
-        fin_update(s, totals);
-    }
-}
 
 // Diagonal preconditioners (identity, P_V): residual, P r and all phase-A sums in one sweep.
 template <typename T>
@@ -557,9 +516,11 @@ __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, Scal* S, in
     const int64_t off = (int64_t)b * N;
     for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
         const int64_t i = off + j;
-        const C2<T> ph = f.phi[i];
+        C2<T> ph = f.phi[i];
+        C2<T> lph = f.Lphi[i];
+        apply_step<T>(f, s, i, ph, lph, acc);
         const T rho = abs2(ph);
-        const C2<T> r = add(f.Lphi[i], scl(ph, beta * rho - lam));
+        const C2<T> r = add(lph, scl(ph, beta * rho - lam));
         f.r[i] = r;
         const C2<T> pr = scl(r, pscale<T>(pre, pv_diag(s, (double)f.V[i], (double)rho)));
         f.pr[i] = pr;
@@ -572,7 +533,7 @@ __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, Scal* S, in
     for (int k = threadIdx.x; k < A_K; k += blockDim.x) P[k] = totals[k];
     if (last_block(pr.counters + b, (unsigned)nbpi, &flag)) {
         reduce_partials<A_K>(pr.parts + (size_t)b * nbpi * A_K, nbpi, red, totals, A_MAXMASK);
-        fin_residual(s, totals[A_RES], totals[A_NF]);
+        fin_residual(s, totals);
         fin_direction(s, totals);
     }
 }
@@ -591,11 +552,18 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         Partials p;
         p.parts = c.parts + (size_t)region * c.region_doubles;
         p.counters = c.counters + (size_t)region * c.B;
-        p.nb = pass_blocks_per_field(g, ax, cb);
+        p.nb = pass_blocks_per_field(g, ax, cb, c.B);
         (void)K;
         return p;
     };
     const Partials none{nullptr, nullptr, 0};
+    // algorithmic bytes of a launch: `reals` real numbers of sizeof(T) per grid point and instance
+    const double unit = (double)sizeof(T) * (double)g.N * (double)c.B;
+    auto tick = [&](const char* name, double reals) {
+        if (c.timer) c.timer->mark(s, name, reals * unit);
+    };
+    const bool rot = g.dim >= 2;  // the B passes along x and y also read phi when omega != 0
+    (void)rot;
     // ---- phase A ----
     int pre = 0, post = 0;
     const bool spectral_p = c.precond == GPE_P_KINETIC || c.precond == GPE_P_COMBINED || c.precond == GPE_P_C1 ||
@@ -607,55 +575,62 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         // diagonal P (identity or P_V): pointwise residual + P r + reductions in one kernel
         const int nbpi = c.pointwise_blocks;
         Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, c.counters + (size_t)R_A1 * c.B, nbpi};
+        tick("step_resid_diag", 21);
         hipLaunchKernelGGL(k_resid_diag<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f, c.S, g.N, nbpi, pre,
                            pr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else if (g.dim == 1) {
         OpResid<T, true> op{f, c.S, pre, post};
+        tick("step_resid_precond_x", 21);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, parts(R_A1, A_K, 0), s)) != hipSuccess) return e;
     } else {
         OpResid<T, false> op{f, c.S, pre, post};
+        tick("step_resid_fwd_x", 17);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, parts(R_A1, A_K, 0), s)) != hipSuccess) return e;
         if (g.dim == 2) {
             OpPMid<T, 1, true, true> y{f.w, c.S};
+            tick("precond_y", 4);
             if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y, none, s)) != hipSuccess) return e;
         } else {
             OpPMid<T, 1, true, false> y1{f.w, c.S};
+            tick("precond_fwd_y", 4);
             if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y1, none, s)) != hipSuccess) return e;
             OpPMid<T, 2, true, true> z{f.w, c.S};
+            tick("precond_z", 4);
             if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), z, none, s)) != hipSuccess) return e;
             OpPMid<T, 1, false, true> y2{f.w, c.S};
+            tick("precond_inv_y", 4);
             if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y2, none, s)) != hipSuccess) return e;
         }
         OpPLast<T> op3{f, c.S, post};
+        tick("precond_inv_x", 13);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op3, parts(R_A3, A_K, 0), s)) != hipSuccess) return e;
     }
     // ---- phase B ----
     if (g.dim == 1) {
         OpLp<T, 0, true, true> op{f, c.S, none, none};
+        tick("dir_Lp_x", 11);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, parts(R_B0, B_K, 0), s)) != hipSuccess) return e;
     } else if (g.dim == 2) {
         OpLp<T, 0, true, false> ox{f, c.S, none, none};
         Partials p0 = parts(R_B0, B_K, 0);
+        tick("dir_Lp_x", 10);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, p0, s)) != hipSuccess) return e;
         OpLp<T, 1, false, true> oy{f, c.S, p0, none};
+        tick("Lp_y_linesearch", 9);
         if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, parts(R_B1, B_K, 1), s)) != hipSuccess) return e;
     } else {
         OpLp<T, 0, true, false> ox{f, c.S, none, none};
         Partials p0 = parts(R_B0, B_K, 0);
+        tick("dir_Lp_x", 10);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, p0, s)) != hipSuccess) return e;
         OpLp<T, 1, false, false> oy{f, c.S, none, none};
         Partials p1 = parts(R_B1, B_K, 1);
+        tick("Lp_y", 8);
         if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, p1, s)) != hipSuccess) return e;
         OpLp<T, 2, false, true> oz{f, c.S, p0, p1};
+        tick("Lp_z_linesearch", 9);
         if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), oz, parts(R_B2, B_K, 2), s)) != hipSuccess) return e;
-    }
-    // ---- phase C ----
-    {
-        const int nbpi = c.pointwise_blocks;
-        Partials pr{c.parts + (size_t)R_C * c.region_doubles, c.counters + (size_t)R_C * c.B, nbpi};
-        hipLaunchKernelGGL(k_update<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f, c.S, g.N, nbpi, pr);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }

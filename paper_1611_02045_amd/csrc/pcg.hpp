@@ -23,8 +23,57 @@ struct IterFields {
 // Partial-sum regions (one per reducing kernel) and their ticket counters.
 enum : int { R_A1 = 0, R_A3 = 1, R_B0 = 2, R_B1 = 3, R_B2 = 4, R_C = 5, R_COUNT = 6 };
 
+// Optional per-kernel timing of an iteration with HIP events recorded on the iteration's stream
+// between consecutive launches (used by gpe_pcg_profile).
+struct KernelTimer {
+    static constexpr int MAX = 16;
+    int n = 0;
+    hipEvent_t ev[MAX + 1] = {};
+    const char* names[MAX] = {};
+    double bytes[MAX] = {};
+    double total_ms[MAX] = {};
+    int64_t launches[MAX] = {};
+    int slots = 0;
+    hipError_t init() {
+        for (int k = 0; k <= MAX; ++k) {
+            hipError_t e = hipEventCreate(&ev[k]);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    void destroy() {
+        for (int k = 0; k <= MAX; ++k)
+            if (ev[k]) (void)hipEventDestroy(ev[k]);
+    }
+    // before a launch: close the previous slot and open slot n
+    void mark(hipStream_t s, const char* name, double b) {
+        if (n >= MAX) return;
+        (void)hipEventRecord(ev[n], s);
+        names[n] = name;
+        bytes[n] = b;
+        ++n;
+    }
+    // after an iteration: record the end, wait, and accumulate the slot durations
+    hipError_t collect(hipStream_t s) {
+        (void)hipEventRecord(ev[n], s);
+        hipError_t e = hipEventSynchronize(ev[n]);
+        if (e != hipSuccess) return e;
+        for (int k = 0; k < n; ++k) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            if (e != hipSuccess) return e;
+            total_ms[k] += ms;
+            launches[k] += 1;
+        }
+        slots = n;
+        n = 0;
+        return hipSuccess;
+    }
+};
+
 template <typename T>
 struct IterCtx {
+    KernelTimer* timer = nullptr;
     Geo g;
     int B;
     const Twiddles* tw;
@@ -37,12 +86,14 @@ struct IterCtx {
     int pointwise_blocks;
 };
 
-// Phase A sums: residual maximum, non-finite flag, and the inner products of the CG update.
+// Phase A sums: residual maximum, non-finite flag, the inner products of the CG update, and the
+// fresh scalars of the (just updated) iterate: <phi, L phi>, sum|phi|^4, ||phi||^2,
+// ||phi_n - phi_{n-1}||_inf.
 enum : int {
     A_RES = 0, A_NF, A_RPR, A_RPPR, A_PRPHI, A_PRPR, A_PRPP, A_RPP, A_PPPHI, A_PPPP, A_RPHI, A_PHIPHI,
-    A_K = 12
+    A_A, A_Q4, A_N2, A_DPHI, A_K = 16
 };
-constexpr unsigned A_MAXMASK = (1u << A_RES) | (1u << A_NF);
+constexpr unsigned A_MAXMASK = (1u << A_RES) | (1u << A_NF) | (1u << A_DPHI);
 
 // Phase B sums: rotation forms, <phat, L phat>, <phi, L phat>, and the line-search polynomials.
 enum : int {
@@ -51,9 +102,27 @@ enum : int {
 };
 constexpr unsigned B_MAXMASK = 1u << B_NF;
 
-// Phase C sums: <phi, L phi>, sum|phi|^4, ||phi||^2, ||phi_{n+1} - phi_n||_inf, non-finite flag.
-enum : int { C_A = 0, C_Q4, C_N2, C_DPHI, C_NF, C_K = 5 };
-constexpr unsigned C_MAXMASK = (1u << C_DPHI) | (1u << C_NF);
+
+// Pending retraction step of the previous iteration, applied pointwise at the start of phase A:
+// phi <- c_phi phi + c_p p, L phi <- c_L L phi + c_Lp L phat (linearity of L), with the fresh
+// sums of the new iterate.  ph and lph hold the loaded values and receive the updated ones.
+template <typename T>
+__device__ __forceinline__ void apply_step(const IterFields<T>& f, const Scal& s, int64_t i, C2<T>& ph, C2<T>& lph,
+                                           double* acc) {
+    if (s.has_step) {
+        const C2<T> np = add(scl(ph, (T)s.c_phi), scl(f.pp[i], (T)s.c_p));
+        const C2<T> nl = add(scl(lph, (T)s.c_L), scl(f.lp[i], (T)s.c_Lp));
+        acc[A_DPHI] = fmax(acc[A_DPHI], sqrt((double)abs2(sub(np, ph))));
+        f.phi[i] = np;
+        f.Lphi[i] = nl;
+        ph = np;
+        lph = nl;
+    }
+    const double r2 = abs2(ph);
+    acc[A_A] += (double)redot(ph, lph);
+    acc[A_Q4] += r2 * r2;
+    acc[A_N2] += r2;
+}
 
 template <typename T>
 __device__ __forceinline__ void res_sums(double* acc, C2<T> r) {

@@ -86,6 +86,7 @@ __global__ void k_scal_from_parts(Scal* S, const double* parts, int restart_cg) 
     if (restart_cg) {
         s.nrm2 = 1.0;
         s.have_prev = 0;
+        s.has_step = 0;
         s.E_prev = E;
         s.best_res = 1e300;
         s.best_n = s.n;
@@ -179,9 +180,12 @@ static hipError_t refresh_instance(const Geo& g, const Twiddles& tw, IterFields<
     if ((e = op_apply(g, f64, 1, tw, f.phi + off, f.V + off, f.Lphi + off, f.w + off, beta, omega, false, s)) !=
         hipSuccess)
         return e;
+    // Mid-phase refreshes stop here: the scalars already describe the iterate that the pending
+    // step produces, and L phi (fresh) is only combined linearly by that step.
+    if (!restart_cg) return hipSuccess;
     double* parts = (double*)red.scalars.ptr + 16;
     if ((e = op_energy(g, f64, tw, f.phi + off, f.V + off, 1.0, omega, red, parts, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scal_from_parts, dim3(1), dim3(64), 0, s, Sd, parts, restart_cg ? 1 : 0);
+    hipLaunchKernelGGL(k_scal_from_parts, dim3(1), dim3(64), 0, s, Sd, parts, 1);
     return hipGetLastError();
 }
 
@@ -235,7 +239,7 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
     c.region_doubles = pa.region_doubles;
     c.counters = (unsigned int*)pa.red->counters.ptr;
     c.precond = pa.precond;
-    c.pointwise_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(512, N / 4096));
+    c.pointwise_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, N / 1024));
     int64_t since_refresh = 0;
     int64_t queued = 0;
     int64_t max_iter = 0;
@@ -275,6 +279,48 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
     pa.final_f_r_is_rp = false;
     return hipSuccess;
 }
+
+// Instrumented iterations: initialise like run_phase, then run exactly `iters` iterations with
+// every launch bracketed by events (the solver must not finish meanwhile: tol = 0 is expected).
+template <typename T>
+hipError_t profile_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, int iters, KernelTimer& timer,
+                         hipStream_t s) {
+    const Geo& g = pa.g;
+    const int64_t N = g.N;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(pa.S, host_S.data(), sizeof(Scal) * pa.B, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return e;
+    if ((e = normalize_all<T>(f, pa.B, N, pa.S, *pa.red, s)) != hipSuccess) return e;
+    if ((e = zero_cg_memory<T>(f, (int64_t)pa.B * N, s)) != hipSuccess) return e;
+    for (int b = 0; b < pa.B; ++b) {
+        if ((e = refresh_instance<T>(g, *pa.tw, f, (int64_t)b * N, pa.S + b, host_S[b].beta, host_S[b].omega, *pa.red,
+                                     true, s)) != hipSuccess)
+            return e;
+    }
+    IterCtx<T> c;
+    c.g = g;
+    c.B = pa.B;
+    c.tw = pa.tw;
+    c.f = f;
+    c.S = pa.S;
+    c.parts = (double*)pa.red->parts.ptr;
+    c.region_doubles = pa.region_doubles;
+    c.counters = (unsigned int*)pa.red->counters.ptr;
+    c.precond = pa.precond;
+    c.pointwise_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, N / 1024));
+    c.timer = &timer;
+    for (int k = 0; k < iters; ++k) {
+        if ((e = enqueue_iteration<T>(c, s)) != hipSuccess) return e;
+        if ((e = timer.collect(s)) != hipSuccess) return e;
+        std::swap(c.f.r, c.f.rp);
+    }
+    return hipMemcpy(host_S.data(), pa.S, sizeof(Scal) * pa.B, hipMemcpyDeviceToHost);
+}
+
+template hipError_t profile_phase<double>(PhaseArgs&, IterFields<double>, std::vector<Scal>&, int, KernelTimer&,
+                                          hipStream_t);
+template hipError_t profile_phase<float>(PhaseArgs&, IterFields<float>, std::vector<Scal>&, int, KernelTimer&,
+                                         hipStream_t);
 
 template hipError_t run_phase<double>(PhaseArgs&, IterFields<double>, std::vector<Scal>&, hipStream_t);
 template hipError_t run_phase<float>(PhaseArgs&, IterFields<float>, std::vector<Scal>&, hipStream_t);

@@ -24,6 +24,10 @@ template <typename T>
 hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, hipStream_t s);
 
 template <typename T>
+hipError_t profile_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, int iters, KernelTimer& timer,
+                         hipStream_t s);
+
+template <typename T>
 hipError_t verify_field(const Geo& g, const Twiddles& tw, const void* phi, const void* V, void* hphi, void* tmp,
                         double beta, double omega, Reduce& red, double out[3], hipStream_t s);
 

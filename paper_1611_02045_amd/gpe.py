@@ -69,6 +69,8 @@ SIGNATURES = {
                                    ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
     "gpe_energy_grad": (_I, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), _VP]),
     "gpe_adjoint_solve": (_I, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
+    "gpe_pcg_profile": (_I, [_VP, _VP, _VP, ctypes.POINTER(PcgOpts), _I, _I, ctypes.POINTER(_D),
+                             ctypes.POINTER(_D), ctypes.c_char_p, _VP]),
     "gpe_last_error": (ctypes.c_char_p, []),
     "gpe_version": (ctypes.c_char_p, []),
 }
@@ -243,6 +245,18 @@ class Plan:
         n = _check(lib().gpe_pcg_history(self._h, buf, cap))
         keys = ("n", "E", "lam", "res", "theta", "beta", "halvings", "restarted")
         return [dict(zip(keys, buf[8 * i: 8 * i + 8])) for i in range(n)]
+
+    def profile(self, V, phi, iters: int = 20, stream=None, **opts):
+        """Per-kernel event timings of `iters` solver iterations: list of (name, avg_ms, bytes)."""
+        o = default_opts(**opts)
+        cap = 16
+        ms = (ctypes.c_double * cap)()
+        by = (ctypes.c_double * cap)()
+        names = ctypes.create_string_buffer(32 * cap)
+        n = _check(lib().gpe_pcg_profile(self._h, self._field(V, "V", False), self._field(phi, "phi"),
+                                         ctypes.byref(o), int(iters), cap, ms, by, names, _stream(stream)))
+        raw = names.raw
+        return [(raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode(), ms[k], by[k]) for k in range(n)]
 
     def adjoint_solve(self, phi_star, V, rhs, stream=None, **opts):
         o = default_opts(**opts)
