@@ -1,5 +1,6 @@
 // C ABI of the solver: options, single solves, history.
 #include <algorithm>
+#include <tuple>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -23,22 +24,154 @@ using namespace gpe;
 
 namespace {
 
-// Run one phase with precision T on fields f, then return the host scalars.
+// Device workspace of one batch of equally sized instances.
+struct BatchWork {
+    Geo g;                 // shared grid (n); box, beta and omega are per instance in the scalars
+    const Twiddles* tw;
+    Reduce* red;
+    DevBuf* scal;          // B solver scalars
+    DevBuf* f64;           // FP64 fields (B instances)
+    DevBuf* f32;           // FP32 fields (B instances)
+    DevBuf* tmp;           // verification scratch (2 fields of one instance)
+};
+
 template <typename T>
-int phase(gpe_plan* plan, IterFields<T> f, std::vector<Scal>& hs, const gpe_pcg_opts_t& o, hipStream_t s) {
+int run(BatchWork& w, int B, IterFields<T> f, std::vector<Scal>& hs, const gpe_pcg_opts_t& o, hipStream_t s) {
     PhaseArgs pa;
-    pa.g = plan->g;
-    pa.B = 1;
-    pa.tw = &plan->tw;
-    pa.S = (Scal*)plan->scal.ptr;
-    pa.red = &plan->red;
-    pa.region_doubles = region_doubles_for(plan->g, 1);
+    pa.g = w.g;
+    pa.B = B;
+    pa.tw = w.tw;
+    pa.S = (Scal*)w.scal->ptr;
+    pa.red = w.red;
+    pa.region_doubles = region_doubles_for(w.g, B);
     pa.precond = o.precond;
     pa.check_every = o.check_every;
     pa.refresh_every = o.refresh_every;
     pa.final_f_r_is_rp = false;
     HIPCHK(run_phase<T>(pa, f, hs, s));
     return GPE_OK;
+}
+
+Geo instance_geo(const Geo&, const gpe_problem_t& p) { return make_geo(p); }
+
+// Solve B instances of one grid.  Inputs phi[b], V[b] are device fields in the caller's type
+// (FP64 when in_f64); phi[b] receives the final iterate.  hist (device) only for B == 1.
+int solve_batch(BatchWork& w, int B, const gpe_problem_t* probs, bool in_f64, const void* const* V, void* const* phi,
+                const gpe_pcg_opts_t& o, double* hist, int64_t hist_cap, gpe_pcg_report_t* reports, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const Geo& g = w.g;
+    const int64_t N = g.N;
+    HIPCHK(reduce_init(*w.red, B, R_COUNT, std::max<size_t>(1 << 18, R_COUNT * region_doubles_for(g, B))));
+    HIPCHK(w.scal->ensure(sizeof(Scal) * (size_t)B));
+    std::vector<Scal> hs(B);
+    for (int b = 0; b < B; ++b) {
+        hs[b] = make_scal(probs[b], instance_geo(g, probs[b]), o);
+        if (hist && b == 0) {
+            hs[b].hist = hist;
+            hs[b].hist_cap = hist_cap;
+        }
+    }
+    hipError_t e = hipSuccess;
+    int st;
+    const bool mixed = o.precision == 1 && in_f64;
+    const size_t cb = in_f64 ? 16 : 8, rb = in_f64 ? 8 : 4;
+    std::vector<int64_t> iters32(B, 0);
+    auto verify_b = [&](int b, const void* ph, const void* Vb, double out[3]) -> hipError_t {
+        const Geo gb = instance_geo(g, probs[b]);
+        hipError_t ee = w.tmp->ensure(2 * cb * (size_t)N);
+        if (ee != hipSuccess) return ee;
+        return in_f64 ? verify_field<double>(gb, *w.tw, ph, Vb, w.tmp->ptr, (char*)w.tmp->ptr + cb * N, probs[b].beta,
+                                             probs[b].omega, *w.red, out, s)
+                      : verify_field<float>(gb, *w.tw, ph, Vb, w.tmp->ptr, (char*)w.tmp->ptr + cb * N, probs[b].beta,
+                                            probs[b].omega, *w.red, out, s);
+    };
+    if (!in_f64) {
+        IterFields<float> f = carve_fields<float>(*w.f32, (int64_t)B * N, &e);
+        HIPCHK(e);
+        for (int b = 0; b < B; ++b) {
+            HIPCHK(copy_bytes(phi[b], f.phi + (int64_t)b * N, cb * N, s));
+            HIPCHK(copy_bytes(V[b], f.V + (int64_t)b * N, rb * N, s));
+        }
+        if ((st = run<float>(w, B, f, hs, o, s)) != GPE_OK) return st;
+        for (int b = 0; b < B; ++b) {
+            iters32[b] = hs[b].n;
+            HIPCHK(copy_bytes(f.phi + (int64_t)b * N, phi[b], cb * N, s));
+        }
+    } else {
+        IterFields<double> f = carve_fields<double>(*w.f64, (int64_t)B * N, &e);
+        HIPCHK(e);
+        if (mixed) {
+            IterFields<float> f32 = carve_fields<float>(*w.f32, (int64_t)B * N, &e);
+            HIPCHK(e);
+            for (int b = 0; b < B; ++b) {
+                HIPCHK(convert_complex(false, phi[b], f32.phi + (int64_t)b * N, N, s));
+                HIPCHK(convert_real(false, V[b], f32.V + (int64_t)b * N, N, s));
+                hs[b].precision = 1;
+                hs[b].tol_res = std::max(o.tol_res_inf, o.switch_res);
+                hs[b].stall_window = 400;
+            }
+            if ((st = run<float>(w, B, f32, hs, o, s)) != GPE_OK) return st;
+            HIPCHK(convert_complex(true, f32.phi, f.phi, (int64_t)B * N, s));
+            for (int b = 0; b < B; ++b) {
+                iters32[b] = hs[b].n;
+                const bool failed = hs[b].status == ST_NONFINITE;
+                hs[b].precision = 0;
+                hs[b].tol_res = o.tol_res_inf;
+                hs[b].stall_window = 0;
+                hs[b].stagnant = 0;
+                hs[b].linesearch_fail = 0;
+                if (!failed && hs[b].n < o.max_iter) {
+                    hs[b].done = 0;
+                    hs[b].status = ST_OK;
+                }
+            }
+        } else {
+            for (int b = 0; b < B; ++b) HIPCHK(copy_bytes(phi[b], f.phi + (int64_t)b * N, cb * N, s));
+        }
+        for (int b = 0; b < B; ++b) HIPCHK(copy_bytes(V[b], f.V + (int64_t)b * N, rb * N, s));
+        // FP64 phase; instances whose tracked residual met tol but whose fresh one did not resume
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            bool any = false;
+            for (int b = 0; b < B; ++b) any = any || !hs[b].done;
+            if (!any) break;
+            if ((st = run<double>(w, B, f, hs, o, s)) != GPE_OK) return st;
+            bool again = false;
+            for (int b = 0; b < B; ++b) {
+                if (hs[b].status != ST_OK || hs[b].n >= o.max_iter || o.tol_energy > 0.0) continue;
+                double chk[3];
+                HIPCHK(verify_b(b, f.phi + (int64_t)b * N, f.V + (int64_t)b * N, chk));
+                if (chk[2] > o.tol_res_inf) {
+                    hs[b].done = 0;
+                    again = true;
+                }
+            }
+            if (!again) break;
+        }
+        for (int b = 0; b < B; ++b) HIPCHK(copy_bytes(f.phi + (int64_t)b * N, phi[b], cb * N, s));
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    const double secs = std::chrono::duration<double>(t1 - t0).count();
+    int worst = GPE_OK;
+    for (int b = 0; b < B; ++b) {
+        double chk[3];
+        HIPCHK(verify_b(b, phi[b], V[b], chk));
+        gpe_pcg_report_t& r = reports[b];
+        std::memset(&r, 0, sizeof(r));
+        r.status = status_of(hs[b].status);
+        r.switched = mixed ? 1 : 0;
+        r.iters = hs[b].n;
+        r.iters_fp32 = in_f64 ? (mixed ? iters32[b] : 0) : hs[b].n;
+        r.restarts = hs[b].restarts;
+        r.halvings = hs[b].halvings;
+        r.E = chk[0];
+        r.lambda = chk[1];
+        r.res_inf = chk[2];
+        r.dE = std::fabs(hs[b].E - hs[b].E_prev);
+        r.dphi_inf = hs[b].dphi;
+        r.seconds = secs;
+        worst = worse_status(worst, r.status);
+    }
+    return worst;
 }
 
 }  // namespace
@@ -70,110 +203,26 @@ int gpe_pcg_solve(gpe_plan_t* plan, const void* V, void* phi_inout, const gpe_pc
     if (!report) { set_error("report is NULL"); return GPE_EINVAL; }
     int st = validate_opts(opts);
     if (st != GPE_OK) return st;
-    const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
     const gpe_pcg_opts_t& o = *opts;
-    const Geo& g = plan->g;
-    const int64_t N = g.N;
-    std::memset(report, 0, sizeof(*report));
-
-    HIPCHK(reduce_init(plan->red, 1, R_COUNT, std::max<size_t>(1 << 18, R_COUNT * region_doubles_for(g, 1))));
-    HIPCHK(plan->scal.ensure(sizeof(Scal)));
-    Scal base = make_scal(plan->prob, g, o);
     int64_t cap = 0;
+    double* hist = nullptr;
     if (o.record_history) {
         cap = std::min<int64_t>(o.max_iter + 1, 1 << 20);
         HIPCHK(plan->hist.ensure(sizeof(double) * 8 * (size_t)cap));
         HIPCHK(hipMemsetAsync(plan->hist.ptr, 0, sizeof(double) * 8 * (size_t)cap, s));
-        base.hist = (double*)plan->hist.ptr;
-        base.hist_cap = cap;
+        hist = (double*)plan->hist.ptr;
     }
-    std::vector<Scal> hs(1, base);
-    hipError_t e = hipSuccess;
-    const bool mixed = o.precision == 1 && plan->f64();
-
-    void* final_phi = nullptr;  // solver-owned final iterate (plan precision or FP64)
-    bool final_is_64 = plan->f64();
-    if (!plan->f64()) {
-        IterFields<float> f = carve_fields<float>(plan->solver, N, &e);
-        HIPCHK(e);
-        HIPCHK(copy_bytes(phi_inout, f.phi, sizeof(float) * 2 * N, s));
-        HIPCHK(copy_bytes(V, f.V, sizeof(float) * N, s));
-        if ((st = phase<float>(plan, f, hs, o, s)) != GPE_OK) return st;
-        final_phi = f.phi;
-        report->iters_fp32 = hs[0].n;
-    } else {
-        IterFields<double> f = carve_fields<double>(plan->solver, N, &e);
-        HIPCHK(e);
-        if (mixed) {
-            IterFields<float> f32 = carve_fields<float>(plan->solver32, N, &e);
-            HIPCHK(e);
-            HIPCHK(convert_complex(false, phi_inout, f32.phi, N, s));
-            HIPCHK(convert_real(false, V, f32.V, N, s));
-            hs[0].precision = 1;
-            hs[0].tol_res = std::max(o.tol_res_inf, o.switch_res);
-            hs[0].stall_window = 100;
-            if ((st = phase<float>(plan, f32, hs, o, s)) != GPE_OK) return st;
-            report->iters_fp32 = hs[0].n;
-            report->switched = 1;
-            HIPCHK(convert_complex(true, f32.phi, f.phi, N, s));
-            const bool failed = hs[0].status == ST_NONFINITE;
-            hs[0].precision = 0;
-            hs[0].tol_res = o.tol_res_inf;
-            hs[0].stall_window = 0;
-            hs[0].stagnant = 0;
-            hs[0].linesearch_fail = 0;
-            if (!failed && hs[0].n < o.max_iter) {
-                hs[0].done = 0;
-                hs[0].status = ST_OK;
-            }
-        } else {
-            HIPCHK(copy_bytes(phi_inout, f.phi, sizeof(double) * 2 * N, s));
-        }
-        HIPCHK(copy_bytes(V, f.V, sizeof(double) * N, s));
-        if (!hs[0].done) {
-            // FP64 phase; resume if the tracked residual met tol while the fresh one did not
-            for (int attempt = 0; attempt < 4; ++attempt) {
-                if ((st = phase<double>(plan, f, hs, o, s)) != GPE_OK) return st;
-                if (hs[0].status != ST_OK || hs[0].n >= o.max_iter) break;
-                double chk[3];
-                HIPCHK(verify_field<double>(g, plan->tw, f.phi, f.V, f.lp, f.w, plan->prob.beta, plan->prob.omega,
-                                            plan->red, chk, s));
-                if (chk[2] <= o.tol_res_inf || o.tol_energy > 0.0) break;
-                hs[0].done = 0;
-            }
-        }
-        final_phi = f.phi;
+    BatchWork w{plan->g, &plan->tw, &plan->red, &plan->scal, &plan->solver, plan->f64() ? &plan->solver32 : &plan->solver,
+                &plan->tmp};
+    const void* Vs[1] = {V};
+    void* phis[1] = {phi_inout};
+    st = solve_batch(w, 1, &plan->prob, plan->f64(), Vs, phis, o, hist, cap, report, s);
+    plan->hist_rows = o.record_history ? std::min<int64_t>(report->iters + 1, cap) : 0;
+    if (st < 0 && st != GPE_EHIP) {
+        set_error(st == GPE_ENONFINITE ? "non-finite value during the iteration" : "line search found no energy decrease");
     }
-    // copy the iterate back and verify it
-    const size_t cbytes = (plan->f64() ? sizeof(double) : sizeof(float)) * 2 * (size_t)N;
-    HIPCHK(copy_bytes(final_phi, phi_inout, cbytes, s));
-    (void)final_is_64;
-    HIPCHK(plan->tmp.ensure(2 * cbytes));
-    double chk[3];
-    if (plan->f64())
-        HIPCHK(verify_field<double>(g, plan->tw, phi_inout, V, plan->tmp.ptr, (char*)plan->tmp.ptr + cbytes,
-                                    plan->prob.beta, plan->prob.omega, plan->red, chk, s));
-    else
-        HIPCHK(verify_field<float>(g, plan->tw, phi_inout, V, plan->tmp.ptr, (char*)plan->tmp.ptr + cbytes,
-                                   plan->prob.beta, plan->prob.omega, plan->red, chk, s));
-    const auto t1 = std::chrono::steady_clock::now();
-    report->status = status_of(hs[0].status);
-    report->iters = hs[0].n;
-    report->restarts = hs[0].restarts;
-    report->halvings = hs[0].halvings;
-    report->E = chk[0];
-    report->lambda = chk[1];
-    report->res_inf = chk[2];
-    report->dE = std::fabs(hs[0].E - hs[0].E_prev);
-    report->dphi_inf = hs[0].dphi;
-    report->seconds = std::chrono::duration<double>(t1 - t0).count();
-    plan->hist_rows = o.record_history ? std::min<int64_t>(hs[0].n + 1, cap) : 0;
-    if (report->status < 0) {
-        set_error(report->status == GPE_ENONFINITE ? "non-finite value during the iteration"
-                                                   : "line search found no energy decrease");
-    }
-    return report->status;
+    return st;
 }
 
 int gpe_pcg_history(gpe_plan_t* plan, double* hist, int cap) {
@@ -249,10 +298,70 @@ int gpe_pcg_profile(gpe_plan_t* plan, const void* V, const void* phi, const gpe_
     return n;
 }
 
-int gpe_pcg_solve_batched(int, const gpe_problem_t*, int, void* const*, void* const*, const gpe_pcg_opts_t*,
-                          gpe_pcg_report_t*, void*) {
-    set_error("gpe_pcg_solve_batched: not implemented yet");
-    return GPE_EUNSUPPORTED;
+int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void* const* V, void* const* phi_inout,
+                          const gpe_pcg_opts_t* opts, gpe_pcg_report_t* reports, void* stream) {
+    if (count < 1 || !probs || !V || !phi_inout || !reports) { set_error("invalid batch arguments"); return GPE_EINVAL; }
+    if (dtype != GPE_F64 && dtype != GPE_F32) { set_error("dtype must be GPE_F64 or GPE_F32"); return GPE_EINVAL; }
+    int st = validate_opts(opts);
+    if (st != GPE_OK) return st;
+    for (int i = 0; i < count; ++i) {
+        if ((st = validate_problem(&probs[i])) != GPE_OK) return st;
+        if (!V[i] || !phi_inout[i]) { set_error("NULL field in batch"); return GPE_EINVAL; }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // group the instances by grid (dim, n): one batch of fused launches per group
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto key = [&](int i) {
+        const gpe_problem_t& p = probs[i];
+        return std::make_tuple(p.dim, p.n[0], p.dim > 1 ? p.n[1] : 1, p.dim > 2 ? p.n[2] : 1);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+    int worst = GPE_OK;
+    size_t pos = 0;
+    while (pos < order.size()) {
+        size_t end = pos;
+        while (end < order.size() && key(order[end]) == key(order[pos])) ++end;
+        const int B = (int)(end - pos);
+        std::vector<gpe_problem_t> gp(B);
+        std::vector<const void*> gV(B);
+        std::vector<void*> gphi(B);
+        for (int b = 0; b < B; ++b) {
+            gp[b] = probs[order[pos + b]];
+            gV[b] = V[order[pos + b]];
+            gphi[b] = phi_inout[order[pos + b]];
+        }
+        Geo g = make_geo(gp[0]);
+        Twiddles tw;
+        Reduce red;
+        DevBuf scal, f64, f32, tmp;
+        hipError_t e = build_twiddles(g, tw);
+        std::vector<gpe_pcg_report_t> rep(B);
+        if (e == hipSuccess) {
+            BatchWork w{g, &tw, &red, &scal, &f64, &f32, &tmp};
+            st = solve_batch(w, B, gp.data(), dtype == GPE_F64, gV.data(), gphi.data(), *opts, nullptr, 0, rep.data(), s);
+        } else {
+            set_error(std::string("twiddle tables: ") + hipGetErrorString(e));
+            st = GPE_EHIP;
+        }
+        (void)hipStreamSynchronize(s);
+        for (int a = 0; a < 3; ++a) {
+            tw.t64[a].release();
+            tw.t32[a].release();
+        }
+        red.parts.release();
+        red.counters.release();
+        red.scalars.release();
+        scal.release();
+        f64.release();
+        f32.release();
+        tmp.release();
+        if (st == GPE_EHIP || st == GPE_EINVAL) return st;
+        for (int b = 0; b < B; ++b) reports[order[pos + b]] = rep[b];
+        worst = worse_status(worst, st);
+        pos = end;
+    }
+    return worst;
 }
 
 int gpe_adjoint_solve(gpe_plan_t*, const void*, const void*, const void*, void*, const gpe_pcg_opts_t*,

@@ -82,4 +82,13 @@ hipError_t op_density(const Geo& g, bool f64, const void* phi, void* out, double
 // Thread-local error message.
 void set_error(const std::string& msg);
 
+// Validates a problem against the supported grids (sets the error message).
+int validate_problem(const gpe_problem_t* p);
+
+// Combine statuses: any error (most negative) wins, else NOT_CONVERGED over OK.
+inline int worse_status(int a, int b) {
+    if (a < 0 || b < 0) return a < b ? a : b;
+    return a > b ? a : b;
+}
+
 }  // namespace gpe

@@ -1,0 +1,108 @@
+"""Batched solves: independent instances on uneven grids (different sizes, boxes, beta, Omega) in
+one iteration loop with per-instance convergence masks, against the FP64 oracle solved one by one."""
+import numpy as np
+import pytest
+
+from gpe_inputs import Problem, harmonic_potential, vortex_seed_2d, batch_instances
+from oracle import gpe_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1611_02045_amd import gpe
+    gpe.lib()
+    return torch
+
+
+def _instances():
+    specs = [((32, 32), 6.0, 20.0, 0.0), ((64, 64), 8.0, 80.0, 0.3), ((32, 32), 7.0, 150.0, 0.6),
+             ((64, 64), 9.0, 40.0, 0.5), ((32, 32), 6.5, 60.0, 0.2), ((64, 32), 8.0, 30.0, 0.4)]
+    out = []
+    for k, (n, L, beta, omega) in enumerate(specs):
+        prob = Problem(2, n, (L, L), beta, omega)
+        out.append((prob, harmonic_potential(prob), vortex_seed_2d(prob, 300 + k)))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_matches_oracle(torch_gpu, precision):
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    inst = _instances()
+    tol = 1e-9
+    Vs = [torch.from_numpy(V).to("cuda") for _, V, _ in inst]
+    phis = [torch.from_numpy(p0).to("cuda") for _, _, p0 in inst]
+    print(f"batched {precision}: {len(inst)} instances", flush=True)
+    st, reps = gpe.pcg_solve_batched([p for p, _, _ in inst], Vs, phis, "f64", tol=tol, max_iter=4000,
+                                     precision=precision)
+    assert st == 0, reps
+    rel = 1e-10 if precision == "fp64" else 1e-6
+    for (prob, V, phi0), rep, phi in zip(inst, reps, phis):
+        ref = O.pcg(prob, V, phi0, tol_res=tol, max_iter=4000)
+        assert rep["status"] == 0 and rep["res_inf"] <= tol
+        assert abs(rep["E"] - ref.E) < rel * abs(ref.E), (prob, rep["E"], ref.E)
+        got = phi.cpu().numpy()
+        assert abs(O.energy(prob, V, got) - ref.E) < rel * abs(ref.E)
+
+
+def test_batched_masks_per_instance(torch_gpu):
+    """A per-instance iteration cap stops only the instances that hit it; the others converge."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    inst = _instances()[:3]
+    probs = [p for p, _, _ in inst]
+    Vs = [torch.from_numpy(V).to("cuda") for _, V, _ in inst]
+    # single solves give the iteration counts
+    counts = []
+    for (prob, V, p0) in inst:
+        plan = gpe.Plan.from_problem(prob, "f64")
+        counts.append(plan.pcg_solve(torch.from_numpy(V).to("cuda"), torch.from_numpy(p0).to("cuda"), tol=1e-9)["iters"])
+    cap = (min(counts) + max(counts)) // 2
+    if max(counts) - min(counts) < 20:
+        pytest.skip("instances converge in too similar iteration counts")
+    phis = [torch.from_numpy(p0).to("cuda") for _, _, p0 in inst]
+    st, reps = gpe.pcg_solve_batched(probs, Vs, phis, "f64", tol=1e-9, max_iter=cap)
+    assert st == 1
+    for c, rep in zip(counts, reps):
+        if c <= cap - 5:
+            assert rep["status"] == 0
+        elif c >= cap + 5:
+            assert rep["status"] == 1 and rep["iters"] == cap
+
+
+def test_batched_f32_storage(torch_gpu):
+    """FP32 plans run FP32 throughout; the energies agree with the oracle to FP32 accuracy."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    inst = _instances()[:2]
+    Vs = [torch.from_numpy(V).to("cuda", torch.float32) for _, V, _ in inst]
+    phis = [torch.from_numpy(p0).to("cuda", torch.complex64) for _, _, p0 in inst]
+    st, reps = gpe.pcg_solve_batched([p for p, _, _ in inst], Vs, phis, "f32", tol=2e-4, max_iter=3000)
+    assert st == 0
+    for (prob, V, phi0), rep in zip(inst, reps):
+        ref = O.pcg(prob, V, phi0, tol_res=1e-9, max_iter=3000)
+        assert abs(rep["E"] - ref.E) < 1e-5 * abs(ref.E)
+
+
+def test_sweep_instances_sample(torch_gpu):
+    """A sample of the 64-instance sweep (Omega ~ U[0,0.95], beta ~ U{100..2000}, M ~ U{128..512},
+    box sized from the Thomas-Fermi radius): each GPU state is re-evaluated by the oracle."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    allinst = batch_instances(64)
+    sample = [bi for bi in allinst if bi.prob.n[0] == 128][:4]
+    probs = [bi.prob for bi in sample]
+    Vs = [torch.from_numpy(bi.V).to("cuda") for bi in sample]
+    phis = [torch.from_numpy(bi.phi0).to("cuda") for bi in sample]
+    st, reps = gpe.pcg_solve_batched(probs, Vs, phis, "f64", tol=1e-8, max_iter=30000, precision="mixed")
+    assert st == 0, [r["status"] for r in reps]
+    for bi, rep, phi in zip(sample, reps, phis):
+        got = phi.cpu().numpy()
+        r, lam = O.residual(bi.prob, bi.V, got)
+        assert float(np.max(np.abs(r))) <= 1.5e-8
+        assert abs(O.energy(bi.prob, bi.V, got) - rep["E"]) < 1e-10 * abs(rep["E"])
