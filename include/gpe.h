@@ -168,6 +168,15 @@ int gpe_energy_grad(gpe_plan_t* plan, const void* phi, const void* V, void* grad
 int gpe_adjoint_solve(gpe_plan_t* plan, const void* phi_star, const void* V, const void* rhs,
                       void* mu, const gpe_pcg_opts_t* opts, gpe_pcg_report_t* report, void* stream);
 
+/* Parameter gradients from an adjoint state mu (the solution of gpe_adjoint_solve for a loss
+ * with d l = Re<g, d phi>): d l / d theta = -Re<mu, (d_theta H) phi_star>.
+ * grad_V: device, real, nullable: -h^d Re(conj(mu) phi_star) per grid point (d l / d V_k).
+ * dl_dbeta: host, nullable: -Re<mu, |phi_star|^2 phi_star>.  dl_domega: host, nullable:
+ * +Re<mu, L_z phi_star> (0 in 1-D).  The loss's explicit dependence on theta (for instance the
+ * energy's own partial derivatives from gpe_energy_grad) is not included.  Synchronises. */
+int gpe_adjoint_param_grads(gpe_plan_t* plan, const void* phi_star, const void* mu, void* grad_V,
+                            double* dl_dbeta, double* dl_domega, void* stream);
+
 /* Instrumented run for measurement: `iters` solver iterations at the precision of
  * opts->precision (0: FP64 fields, 1: FP32 fields; an FP32 plan always uses FP32) from phi
  * (device, left unchanged), with every kernel launch of an iteration bracketed by HIP events

@@ -515,3 +515,93 @@ def dense_operator(prob, apply) -> np.ndarray:
         e[k] = 1.0
         A[:, k] = apply(e.reshape(prob.shape)).ravel()
     return A
+
+
+# ----------------------------------------------------------------------------------------------
+# Implicit differentiation of the ground state (second-order conditions of Section 2)
+# ----------------------------------------------------------------------------------------------
+
+def hessian_apply(prob, V, phi, f) -> np.ndarray:
+    """(1/2) nabla^2 E(phi)[f] = H_phi f + 2 eta Re(conj(phi) f) phi: the real-linear second
+    derivative whose quadratic form is ``hessian_form`` (Section 2, completed interaction term)."""
+    return (linear_part(prob, V, f) + prob.beta * np.abs(phi) ** 2 * f
+            + 2.0 * prob.beta * (np.conj(phi) * f).real * phi)
+
+
+def project_gauge(prob, phi, f) -> np.ndarray:
+    """Projection onto {phi, i phi}^perp in the real inner product Re<.,.>: removes the sphere's
+    normal direction and the global-phase (gauge) null direction of the Hessian.  phi is unit."""
+    iphi = 1j * phi
+    return f - inner(prob, phi, f).real * phi - inner(prob, iphi, f).real * iphi
+
+
+def adjoint_solve(prob, V, phi, rhs, *, tol: float = 1e-10, max_iter: int = 5000, precond: str = "combined"):
+    """Solve A mu = Pi rhs with A = Pi ((1/2) nabla^2 E(phi) - lambda) Pi on {phi, i phi}^perp by
+    preconditioned linear CG in the real inner product (A is SPD there at a local minimum:
+    the second-order condition of Section 2).  The preconditioner is Pi P Pi with the solver's P
+    at phi.  Returns (mu, iterations, final relative residual)."""
+    lam = chemical_potential(prob, V, phi)
+    alpha = characteristic_energy(prob, V, phi)
+
+    def A(f):
+        return project_gauge(prob, phi, hessian_apply(prob, V, phi, f) - lam * f)
+
+    def P(f):
+        return project_gauge(prob, phi, apply_preconditioner(prob, precond, V, phi, project_gauge(prob, phi, f),
+                                                             alpha=alpha))
+
+    b = project_gauge(prob, phi, rhs)
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = P(r)
+    p = z.copy()
+    rz = inner(prob, r, z).real
+    b2 = math.sqrt(inner(prob, b, b).real)
+    it = 0
+    rel = 0.0 if b2 == 0 else 1.0
+    for it in range(max_iter):
+        rel = math.sqrt(inner(prob, r, r).real) / b2 if b2 > 0 else 0.0
+        if rel <= tol:
+            break
+        q = A(p)
+        pq = inner(prob, p, q).real
+        if pq <= 0.0:
+            raise ValueError("the projected Hessian is not positive definite (not a local minimum)")
+        a = rz / pq
+        x = x + a * p
+        r = r - a * q
+        z = P(r)
+        rz_new = inner(prob, r, z).real
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it, rel
+
+
+def density_loss(prob, phi, rho_target) -> float:
+    """h^d sum (|phi|^2 - rho_target)^2."""
+    return cell(prob) * float(np.sum((np.abs(phi) ** 2 - rho_target) ** 2))
+
+
+def density_loss_gradient(prob, phi, rho_target) -> np.ndarray:
+    """g with d(density_loss) = Re<g, d phi>: g = 4 (|phi|^2 - rho_target) phi."""
+    return 4.0 * (np.abs(phi) ** 2 - rho_target) * phi
+
+
+def implicit_gradient(prob, V, phi, g, dV_list, *, tol: float = 1e-11):
+    """Gradient of  l(theta) = E(phi*; theta) + G(phi*)  at a converged ground state phi*, where
+    d G = Re<g, d phi>.  By the envelope property the energy contributes its partial derivatives
+    only; G contributes -Re<mu, (d_theta H) phi*> with A mu = Pi g.  dV_list holds dV/dtheta for
+    the potential parameters; the last two entries of the result are d/d eta and d/d Omega."""
+    mu, _, _ = adjoint_solve(prob, V, phi, g, tol=tol)
+    w = cell(prob)
+    rho = np.abs(phi) ** 2
+    out = []
+    for dV in dV_list:
+        out.append(w * float(np.sum(dV * rho)) - inner(prob, mu, dV * phi).real)
+    out.append(0.5 * w * float(np.sum(rho * rho)) - inner(prob, mu, rho * phi).real)
+    if prob.dim >= 2:
+        lz = angular_momentum(prob, phi)
+        out.append(-inner(prob, phi, lz).real - inner(prob, mu, -lz).real)
+    else:
+        out.append(0.0)
+    return np.array(out), mu

@@ -364,10 +364,4 @@ int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void
     return worst;
 }
 
-int gpe_adjoint_solve(gpe_plan_t*, const void*, const void*, const void*, void*, const gpe_pcg_opts_t*,
-                      gpe_pcg_report_t*, void*) {
-    set_error("gpe_adjoint_solve: not implemented yet");
-    return GPE_EUNSUPPORTED;
-}
-
 }  // extern "C"

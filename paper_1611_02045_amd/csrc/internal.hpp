@@ -59,6 +59,9 @@ hipError_t reduce_init(Reduce& r, int instances, int slots, size_t part_doubles)
 hipError_t op_apply(const Geo& g, bool f64, int B, const Twiddles& tw, const void* f, const void* V,
                     void* out, void* tmp, double beta, double omega, bool nonlinear, hipStream_t s);
 
+// out = -L_z f (dim >= 2), tmp: one field of workspace.
+hipError_t op_rotation(const Geo& g, bool f64, const Twiddles& tw, const void* f, void* out, void* tmp, hipStream_t s);
+
 // Energy parts of one field: dst (device, 4 doubles) <- {kinetic, potential, interaction, rotation}.
 hipError_t op_energy(const Geo& g, bool f64, const Twiddles& tw, const void* phi, const void* V,
                      double beta, double omega, Reduce& red, double* dst, hipStream_t s);

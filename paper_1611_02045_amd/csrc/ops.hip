@@ -35,6 +35,7 @@ struct OpApply {
     const T* V;        // used on the last axis
     double beta, omega;
     int last, nonlinear;
+    double kin = 1.0;  // weight of the kinetic symbol (0: rotation part only)
     struct State { C2<T> f0[8]; };
     __device__ bool skip(const Geo&, int) const { return false; }
     __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
@@ -48,7 +49,7 @@ struct OpApply {
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const double xi = freq_of(lc.k(s), lc.M, g.L[AX]);
-            v[s] = scl(v[s], (T)((0.5 * xi * xi + rot * xi) * inv));
+            v[s] = scl(v[s], (T)((0.5 * kin * xi * xi + rot * xi) * inv));
         }
     }
     __device__ void store(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&)[1]) const {
@@ -57,7 +58,7 @@ struct OpApply {
             const int64_t i = lc.at(s);
             C2<T> o = v[s];
             if (acc) o = add(o, acc[i]);
-            if (last) {
+            if (last && V) {
                 T w = V[i - lc.off_b];
                 if (nonlinear) w += (T)beta * abs2(st.f0[s]);
                 o = add(o, scl(st.f0[s], w));
@@ -90,6 +91,24 @@ static hipError_t apply_t(const Geo& g, int B, const Twiddles& tw, const void* f
     if ((e = launch_pass<T, 1>(g, B, tw.get(1, f64), oy, none, s)) != hipSuccess) return e;
     OpApply<T, 2> oz{F, (const C2<T>*)tmp, (C2<T>*)out, (const T*)V, beta, omega, 1, nl};
     return launch_pass<T, 2>(g, B, tw.get(2, f64), oz, none, s);
+}
+
+// out = R f with R = -L_z (rotation symbol with omega = 1, no kinetic, no potential); dim >= 2.
+template <typename T>
+static hipError_t rotation_t(const Geo& g, const Twiddles& tw, const void* f, void* out, void* tmp, hipStream_t s) {
+    const bool f64 = sizeof(T) == 8;
+    const C2<T>* F = (const C2<T>*)f;
+    Partials none{nullptr, nullptr, 0};
+    hipError_t e;
+    OpApply<T, 0> ox{F, nullptr, (C2<T>*)tmp, nullptr, 0.0, 1.0, 0, 0, 0.0};
+    if ((e = launch_pass<T, 0>(g, 1, tw.get(0, f64), ox, none, s)) != hipSuccess) return e;
+    // the y pass completes R (no z part in 3-D: L_z acts in the xy-planes)
+    OpApply<T, 1> oy{F, (const C2<T>*)tmp, (C2<T>*)out, nullptr, 0.0, 1.0, 1, 0, 0.0};
+    return launch_pass<T, 1>(g, 1, tw.get(1, f64), oy, none, s);
+}
+
+hipError_t op_rotation(const Geo& g, bool f64, const Twiddles& tw, const void* f, void* out, void* tmp, hipStream_t s) {
+    return f64 ? rotation_t<double>(g, tw, f, out, tmp, s) : rotation_t<float>(g, tw, f, out, tmp, s);
 }
 
 hipError_t op_apply(const Geo& g, bool f64, int B, const Twiddles& tw, const void* f, const void* V, void* out,

@@ -69,6 +69,7 @@ SIGNATURES = {
                                    ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
     "gpe_energy_grad": (_I, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), _VP]),
     "gpe_adjoint_solve": (_I, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
+    "gpe_adjoint_param_grads": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), _VP]),
     "gpe_pcg_profile": (_I, [_VP, _VP, _VP, ctypes.POINTER(PcgOpts), _I, _I, ctypes.POINTER(_D),
                              ctypes.POINTER(_D), ctypes.c_char_p, _VP]),
     "gpe_last_error": (ctypes.c_char_p, []),
@@ -259,6 +260,9 @@ class Plan:
         return [(raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode(), ms[k], by[k]) for k in range(n)]
 
     def adjoint_solve(self, phi_star, V, rhs, stream=None, **opts):
+        """mu with A mu = Pi rhs on {phi*, i phi*}^perp (relative residual tolerance `tol`)."""
+        opts.setdefault("tol", 1e-10)
+        opts.setdefault("max_iter", 5000)
         o = default_opts(**opts)
         rep = PcgReport()
         mu = torch.empty_like(rhs)
@@ -266,6 +270,16 @@ class Plan:
                                        self._field(rhs, "rhs"), self._field(mu, "mu"), ctypes.byref(o),
                                        ctypes.byref(rep), _stream(stream)))
         return mu, rep.as_dict()
+
+    def adjoint_param_grads(self, phi_star, mu, stream=None):
+        """(grad_V field, dl/dbeta, dl/domega) of the adjoint part -Re<mu, (d_theta H) phi*>."""
+        gV = torch.empty(self.shape, dtype=self.real_dtype, device=phi_star.device)
+        db = ctypes.c_double()
+        do = ctypes.c_double()
+        _check(lib().gpe_adjoint_param_grads(self._h, self._field(phi_star, "phi_star"), self._field(mu, "mu"),
+                                             self._field(gV, "grad_V", False), ctypes.byref(db), ctypes.byref(do),
+                                             _stream(stream)))
+        return gV, db.value, do.value
 
 
 def pcg_solve_batched(problems, Vs, phis, dtype: str = "f64", stream=None, **opts):
