@@ -62,7 +62,7 @@ int solve_batch(BatchWork& w, int B, const gpe_problem_t* probs, bool in_f64, co
     const Geo& g = w.g;
     const int64_t N = g.N;
     HIPCHK(reduce_init(*w.red, B, R_COUNT, std::max<size_t>(1 << 18, R_COUNT * region_doubles_for(g, B))));
-    HIPCHK(w.scal->ensure(sizeof(Scal) * (size_t)B));
+    HIPCHK(w.scal->ensure(3 * sizeof(Scal) * (size_t)B));
     std::vector<Scal> hs(B);
     for (int b = 0; b < B; ++b) {
         hs[b] = make_scal(probs[b], instance_geo(g, probs[b]), o);
@@ -242,7 +242,7 @@ int gpe_pcg_profile(gpe_plan_t* plan, const void* V, const void* phi, const gpe_
     const Geo& g = plan->g;
     const int64_t N = g.N;
     HIPCHK(reduce_init(plan->red, 1, R_COUNT, std::max<size_t>(1 << 18, R_COUNT * region_doubles_for(g, 1))));
-    HIPCHK(plan->scal.ensure(sizeof(Scal)));
+    HIPCHK(plan->scal.ensure(3 * sizeof(Scal)));
     gpe_pcg_opts_t o = *opts;
     o.tol_res_inf = 0.0;
     o.tol_energy = 0.0;

@@ -82,7 +82,7 @@ struct Scal {
     // counters and flags
     int64_t n, restarts, halvings, iters_fp32;
     int32_t done, status, have_prev, linesearch_fail;
-    int32_t stagnant, nonfinite, force_gradient, precision;
+    int32_t stagnant, nonfinite, b_phase, precision;   // b_phase: direction partials are pending
     // options copied per instance
     double tol_res, tol_energy, theta_default;
     int32_t method, beta_rule, max_halvings, precond;

@@ -26,7 +26,7 @@ __device__ __forceinline__ double rot_coef(const Geo& g, const LineCtx& lc, doub
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX>
 struct OpApply {
-    static constexpr bool FWD = true, INV = true, FINAL = false;
+    static constexpr bool FWD = true, INV = true, SCALARS = false;
     static constexpr int K = 0;
     static constexpr unsigned MAXMASK = 0;
     const C2<T>* f;
@@ -37,7 +37,6 @@ struct OpApply {
     int last, nonlinear;
     double kin = 1.0;  // weight of the kinetic symbol (0: rotation part only)
     struct State { C2<T> f0[8]; };
-    __device__ bool skip(const Geo&, int) const { return false; }
     __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
 #pragma unroll
         for (int s = 0; s < 8; ++s) st.f0[s] = v[s] = f[lc.at(s)];
@@ -66,7 +65,6 @@ struct OpApply {
             out[i] = o;
         }
     }
-    __device__ void finalize(const Geo&, int, const double*) const {}
 };
 
 template <typename T>
@@ -123,14 +121,13 @@ hipError_t op_apply(const Geo& g, bool f64, int B, const Twiddles& tw, const voi
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX>
 struct OpEnergy {
-    static constexpr bool FWD = true, INV = false, FINAL = false;
+    static constexpr bool FWD = true, INV = false, SCALARS = false;
     static constexpr int K = 4;
     static constexpr unsigned MAXMASK = 0;
     const C2<T>* phi;
     const T* V;
     double omega;
     struct State { C2<T> f0[8]; };
-    __device__ bool skip(const Geo&, int) const { return false; }
     __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
 #pragma unroll
         for (int s = 0; s < 8; ++s) st.f0[s] = v[s] = phi[lc.at(s)];
@@ -157,7 +154,6 @@ struct OpEnergy {
             acc[3] += r * r;
         }
     }
-    __device__ void finalize(const Geo&, int, const double*) const {}
 };
 
 // Sum the per-block partials of up to three passes and scale into {kin, pot, inter, rot}.
@@ -237,7 +233,7 @@ __device__ __forceinline__ T pv_scale(int kind, double alpha, T V, T rho, double
 
 template <typename T, int AX, bool F, bool I>
 struct OpPre {
-    static constexpr bool FWD = F, INV = I, FINAL = false;
+    static constexpr bool FWD = F, INV = I, SCALARS = false;
     static constexpr int K = 0;
     static constexpr unsigned MAXMASK = 0;
     const C2<T>* in;
@@ -248,7 +244,6 @@ struct OpPre {
     double beta;
     int pre, post;
     struct State {};
-    __device__ bool skip(const Geo&, int) const { return false; }
     __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
         const double a = *alpha;
 #pragma unroll
@@ -289,7 +284,6 @@ struct OpPre {
             out[i] = o;
         }
     }
-    __device__ void finalize(const Geo&, int, const double*) const {}
 };
 
 template <typename T>

@@ -5,8 +5,11 @@
 //   decode line -> Op::load (prologue, fills the 8 registers) -> forward FFT (optional)
 //   -> Op::spectral (multiplier and spectral reductions) -> inverse FFT (optional)
 //   -> Op::store (epilogue: combine, write, pointwise reductions)
-//   -> deterministic block reduction of Op::K sums into per-block partials
-//   -> optionally, in the last block of each instance, Op::finalize (FP64 scalar logic).
+//   -> deterministic block reduction of Op::K sums into per-block partials.
+// Solver passes (Op::SCALARS) first build the instance's FP64 scalar state in LDS with Op::begin:
+// every block reduces the partials of the previous pass in the same fixed order and runs the same
+// scalar logic, so all blocks agree without atomics or fences (the kernel boundary makes the
+// previous pass's partials visible), and one block per instance publishes the new state.
 // Field layout: x fastest; a batch of B equally sized instances is stored back to back.  For the
 // x axis consecutive lanes walk along one line (stride 1, coalesced); for y and z consecutive
 // lanes walk across C adjacent lines (adjacent x, coalesced), and each thread keeps its 8
@@ -26,6 +29,7 @@ struct LineCtx {
     int64_t base;   // offset of point 0 of the line in the batched field
     int64_t stride; // distance between consecutive points of the line
     int64_t off_b;  // b * N
+    const Scal* sc; // the instance's scalar state in LDS (solver passes only)
     __device__ __forceinline__ int64_t at(int s) const { return base + (int64_t)(t + s * TPL) * stride; }
     __device__ __forceinline__ int k(int s) const { return t + s * TPL; }
 };
@@ -110,33 +114,40 @@ __device__ __forceinline__ void reduce_partials(const double* parts, int nb, dou
 }
 
 // The pass kernel.  Op must provide:
-//   static constexpr bool FWD, INV;  static constexpr int K;  static constexpr bool FINAL;
-//   static constexpr unsigned MAXMASK;  (bit k set: sum k is a max-reduction of non-negatives)
-//   struct State;   __device__ bool skip(const Geo&, int b) const;
+//   static constexpr bool FWD, INV;  static constexpr int K;  static constexpr unsigned MAXMASK;
+//   static constexpr bool SCALARS;   (bit k of MAXMASK set: sum k is a max-reduction)
+//   struct State;
+//   __device__ void begin(const Geo&, int b, int blk_in_inst, double* red, Scal* s) const;  // if SCALARS
 //   __device__ void load(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
 //   __device__ void spectral(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K],
 //                            C2<T>* buf, const C2<T>* tw) const;   (buf/tw: to transform more lines)
 //   __device__ void store(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
-//   __device__ void finalize(const Geo&, int b, const double* totals) const;   // if FINAL
-// K sums are accumulated per thread in FP64 and reduced deterministically.
+// K sums are accumulated per thread in FP64 and reduced deterministically into pr.parts.
 template <typename T, int AX, class Op, int MAXT>
 __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op,
                                                     Partials pr) {
     extern __shared__ double4 smem_raw[];
-    const LineCtx lc = decode_line<AX>(g, C);
-    if (op.skip(g, lc.b)) return;  // uniform per block: all lines of a block share one instance
+    LineCtx lc = decode_line<AX>(g, C);
     C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
     C2<T>* buf = tw + lc.M + (size_t)lc.c * line_stride(lc.M);
     size_t off = sizeof(C2<T>) * ((size_t)lc.M + (size_t)C * line_stride(lc.M));
     off = (off + 15) & ~(size_t)15;
     double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem_raw) + off);
+    const int blk_in_inst = pr.nb > 0 ? (int)(blockIdx.x % (unsigned)pr.nb) : 0;
+    lc.sc = nullptr;
+    if constexpr (Op::SCALARS) {
+        __shared__ Scal s_local;
+        op.begin(g, lc.b, blk_in_inst, red, &s_local);  // all threads; ends with a barrier
+        if (s_local.done) return;                       // uniform per block (one instance per block)
+        lc.sc = &s_local;
+    }
     load_twiddles(tw, twg, lc.M);
 
     typename Op::State st;
     C2<T> v[8];
     double acc[Op::K > 0 ? Op::K : 1];
 #pragma unroll
-    for (int k = 0; k < (Op::K > 0 ? Op::K : 1); ++k) acc[k] = 0.0;
+    for (int k = 0; k < (Op::K > 0 ? Op::K : 1); ++k) acc[k] = ((Op::MAXMASK >> k) & 1u) ? 0.0 : 0.0;
 
     op.load(g, lc, st, v, acc);
     if (Op::FWD) fft_line<T, -1>(v, buf, tw, lc.t, lc.lg);
@@ -148,16 +159,8 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
         const int nw = (blockDim.x + 63) >> 6;
         double* outK = red + (size_t)nw * Op::K;
         block_reduce<Op::K>(acc, red, outK, Op::MAXMASK);
-        const int blk_in_inst = (int)(blockIdx.x % (unsigned)pr.nb);
         double* P = pr.parts + ((size_t)lc.b * pr.nb + blk_in_inst) * Op::K;
         for (int k = threadIdx.x; k < Op::K; k += blockDim.x) P[k] = outK[k];
-        if constexpr (Op::FINAL) {
-            int* flag = reinterpret_cast<int*>(outK + Op::K);
-            if (last_block(pr.counters + lc.b, (unsigned)pr.nb, flag)) {
-                reduce_partials<Op::K>(pr.parts + (size_t)lc.b * pr.nb * Op::K, pr.nb, red, outK, Op::MAXMASK);
-                op.finalize(g, lc.b, outK);
-            }
-        }
     }
 }
 

@@ -12,9 +12,13 @@
 //        of the next iteration's phase A, which also reduces the fresh <phi, L phi>, sum|phi|^4
 //        and ||phi||^2 of the new iterate.
 //
-// Scalar logic runs in the last workgroup of each reducing kernel (FP64, deterministic order):
-// the convergence test after A's first pass, beta_cg and the descent test after A, and the step
-// after B.  lambda, lambda~ and E of the next iterate follow exactly from the line-search sums
+// Scalar logic (FP64) runs at the start of the pass that consumes a reduction: every workgroup
+// reduces the previous pass's per-block partials in the same fixed order and runs the same
+// logic, so all workgroups agree bit for bit without atomics, fences or a serial tail; one
+// workgroup per instance publishes the state into a versioned slot (S_step after the step, S_res
+// after the convergence test, S_dir after the CG direction), so no pass writes a slot it reads.
+// The convergence test runs at the start of the first middle pass, beta_cg and the descent test
+// at the start of the direction pass, and the step at the start of the next iteration.  lambda, lambda~ and E of the next iterate follow exactly from the line-search sums
 // (they are quadratic and quartic forms in (cos t, sin t)), so the residual of iteration n+1 can
 // be formed in the same pass that applies the step.  Every kernel returns at once for instances
 // whose `done` flag is set, so surplus iterations queued after convergence are no-ops.
@@ -230,26 +234,84 @@ __device__ void fin_step(Scal& S, const double* t) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Phase A, first pass (x): residual, ||r||_inf, P_V^{1/2} (or P_V) prologue, forward x.
+// Scalar-state helpers for the passes
+// ---------------------------------------------------------------------------------------------
+// Copy the instance's state into LDS; only the publishing block keeps the history pointer.
+__device__ __forceinline__ void state_load(const Scal* in, int b, int blk, Scal* s) {
+    if (threadIdx.x == 0) {
+        *s = in[b];
+        if (blk != 0) s->hist = nullptr;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void state_publish(Scal* out, int b, int blk, const Scal* s) {
+    __syncthreads();
+    if (blk == 0 && threadIdx.x == 0) {
+        Scal c = *s;
+        c.hist = out[b].hist;  // keep the instance's history pointer
+        out[b] = c;
+    }
+}
+
+// Totals of K sums of instance b over the producing pass's blocks (LDS `out`, K doubles).
+template <int K>
+__device__ __forceinline__ void absorb(const Partials& P, int b, unsigned mask, double* red, double* out) {
+    reduce_partials<K>(P.parts + (size_t)b * P.nb * K, P.nb, red, out, mask);
+}
+
+// The step: totals of the direction passes (x, y, z partial regions, B sums).
+__device__ void absorb_step(const Partials& p0, const Partials& p1, const Partials& p2, int b, double* red,
+                            Scal* s) {
+    __shared__ double tot[B_K];
+    __shared__ double part[B_K];
+    for (int k = threadIdx.x; k < B_K; k += blockDim.x) tot[k] = 0.0;
+    __syncthreads();
+    auto merge = [&](const Partials& P) {
+        if (!P.parts) return;
+        absorb<B_K>(P, b, B_MAXMASK, red, part);
+        for (int k = threadIdx.x; k < B_K; k += blockDim.x) {
+            const bool mx = (B_MAXMASK >> k) & 1u;
+            tot[k] = mx ? fmax(tot[k], part[k]) : tot[k] + part[k];
+        }
+        __syncthreads();
+    };
+    merge(p0);
+    merge(p1);
+    merge(p2);
+    fin_step(*s, tot);
+    if (threadIdx.x == 0) s->b_phase = 0;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Phase A, first pass (x): [step from the direction sums], the pending retraction applied to
+// phi and L phi, residual, ||r||_inf, fresh scalars, P_V^{1/2} (or P_V) prologue, forward x.
 // With ONE (1-D) the pass also applies the multiplier, the inverse and the epilogue, i.e. the
 // whole preconditioner and the CG reductions.
 // ---------------------------------------------------------------------------------------------
 template <typename T, bool ONE>
 struct OpResid {
-    static constexpr bool FWD = true, INV = ONE, FINAL = true;
+    static constexpr bool FWD = true, INV = ONE, SCALARS = true;
     static constexpr int K = A_K;
     static constexpr unsigned MAXMASK = A_MAXMASK;
     IterFields<T> f;
-    Scal* S;
+    const Scal* Sin;  // S_dir
+    Scal* Sout;       // S_step
+    Partials pb0, pb1, pb2;
     int pre, post;
     struct State {
         C2<T> ph[ONE ? 8 : 1];
         C2<T> r[ONE ? 8 : 1];
         double d[ONE ? 8 : 1];
     };
-    __device__ bool skip(const Geo&, int b) const { return S[b].done != 0; }
-    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
-        const Scal& s = S[lc.b];
+    __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s) const {
+        state_load(Sin, b, blk, s);
+        if (!s->done && s->b_phase) absorb_step(pb0, pb1, pb2, b, red, s);
+        state_publish(Sout, b, blk, s);
+    }
+    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K]) const {
+        const Scal& s = *lc.sc;
         const T lam = (T)s.lam, beta = (T)s.beta;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -271,10 +333,10 @@ struct OpResid {
             }
         }
     }
-    __device__ void spectral(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K], C2<T>*,
+    __device__ void spectral(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[K], C2<T>*,
                              const C2<T>*) const {
         if constexpr (ONE) {
-            const Scal& s = S[lc.b];
+            const Scal& s = *lc.sc;
             const double invN = 1.0 / lc.M;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -282,7 +344,6 @@ struct OpResid {
                 v[q] = scl(v[q], (T)(invN / (s.lamt + 0.5 * k * k)));
             }
         }
-        (void)acc;
     }
     __device__ void store(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K]) const {
         if constexpr (!ONE) {
@@ -298,33 +359,42 @@ struct OpResid {
             }
         }
     }
-    __device__ void finalize(const Geo&, int b, const double* t) const {
-        fin_residual(S[b], t);
-        if constexpr (ONE) fin_direction(S[b], t);
-    }
 };
 
 // ---------------------------------------------------------------------------------------------
 // Phase A, middle passes (y, z): forward and/or inverse transform with the kinetic multiplier
 // 1/(lambda~ + |k|^2/2) (with the 1/N of the inverse transforms) on the pass that does both.
+// The first middle pass (ABS) runs the convergence test on the first pass's sums.
 // ---------------------------------------------------------------------------------------------
-template <typename T, int AX, bool F, bool I>
+template <typename T, int AX, bool F, bool I, bool ABS>
 struct OpPMid {
-    static constexpr bool FWD = F, INV = I, FINAL = false;
+    static constexpr bool FWD = F, INV = I, SCALARS = true;
     static constexpr int K = 0;
     static constexpr unsigned MAXMASK = 0;
     C2<T>* w;
-    Scal* S;
+    const Scal* Sin;  // ABS: S_step; otherwise S_res
+    Scal* Sout;       // ABS: S_res
+    Partials pa1;
     struct State {};
-    __device__ bool skip(const Geo&, int b) const { return S[b].done != 0; }
-    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
+    __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s) const {
+        state_load(Sin, b, blk, s);
+        if constexpr (ABS) {
+            if (!s->done) {
+                __shared__ double tot[A_K];
+                absorb<A_K>(pa1, b, A_MAXMASK, red, tot);
+                fin_residual(*s, tot);
+            }
+            state_publish(Sout, b, blk, s);
+        }
+    }
+    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1]) const {
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = w[lc.at(q)];
     }
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
                              const C2<T>*) const {
         if constexpr (F && I) {
-            const Scal& s = S[lc.b];
+            const Scal& s = *lc.sc;
             double ko;
             if (AX == 1) {
                 const double xi = freq_of(lc.i1, g.n[0], s.L[0]);
@@ -346,7 +416,6 @@ struct OpPMid {
 #pragma unroll
         for (int q = 0; q < 8; ++q) w[lc.at(q)] = v[q];
     }
-    __device__ void finalize(const Geo&, int, const double*) const {}
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -354,22 +423,22 @@ struct OpPMid {
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 struct OpPLast {
-    static constexpr bool FWD = false, INV = true, FINAL = true;
+    static constexpr bool FWD = false, INV = true, SCALARS = true;
     static constexpr int K = A_K;
     static constexpr unsigned MAXMASK = A_MAXMASK;
     IterFields<T> f;
-    Scal* S;
+    const Scal* Sin;  // S_res
     int post;
     struct State {};
-    __device__ bool skip(const Geo&, int b) const { return S[b].done != 0; }
-    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
+    __device__ void begin(const Geo&, int b, int blk, double*, Scal* s) const { state_load(Sin, b, blk, s); }
+    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[K]) const {
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = f.w[lc.at(q)];
     }
     __device__ void spectral(const Geo&, const LineCtx&, State&, C2<T> (&)[8], double (&)[K], C2<T>*,
                              const C2<T>*) const {}
     __device__ void store(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K]) const {
-        const Scal& s = S[lc.b];
+        const Scal& s = *lc.sc;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
@@ -380,30 +449,47 @@ struct OpPLast {
             cg_sums<T>(acc, f.r[i], pr, f.rp[i], f.pp[i], ph);
         }
     }
-    __device__ void finalize(const Geo&, int b, const double* t) const { fin_direction(S[b], t); }
 };
 
 // ---------------------------------------------------------------------------------------------
 // Phase B: p = -P r + beta_cg p_{n-1} - rho phi (written over p_{n-1}), phat = p/||p||, and
 // L phat = sum_a F_a^{-1}[sigma_a F_a phat] + V phat.  When omega != 0 the passes along x and y
 // also transform phi (forward only) to accumulate <phi, R phi>, Re<phi, R phat>, <phat, R phat>
-// (Parseval per line), which keeps lambda~ exact without a separate rotation field.
+// (Parseval per line), which keeps lambda~ exact without a separate rotation field.  The first
+// pass runs the CG direction logic (and, on the one-pass paths, the convergence test).
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX, bool FIRST, bool LAST>
 struct OpLp {
-    static constexpr bool FWD = true, INV = true, FINAL = LAST;
+    static constexpr bool FWD = true, INV = true, SCALARS = true;
     static constexpr int K = B_K;
     static constexpr unsigned MAXMASK = B_MAXMASK;
     IterFields<T> f;
-    Scal* S;
-    Partials prev0, prev1;  // partials of the earlier B passes (reduced by the last one)
+    const Scal* Sin;   // FIRST: S_res (or S_step on the one-pass paths); otherwise S_dir
+    Scal* Sout;        // FIRST: S_dir
+    Partials pres;     // FIRST: sums for the convergence test (one-pass paths), else empty
+    Partials pdir;     // FIRST: sums for the CG direction
     struct State {
         C2<T> ph[8];
         C2<T> p[8];
     };
-    __device__ bool skip(const Geo&, int b) const { return S[b].done != 0; }
-    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
-        const Scal& s = S[lc.b];
+    __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s) const {
+        state_load(Sin, b, blk, s);
+        if constexpr (FIRST) {
+            __shared__ double tot[A_K];
+            if (!s->done && pres.parts) {
+                absorb<A_K>(pres, b, A_MAXMASK, red, tot);
+                fin_residual(*s, tot);
+            }
+            if (!s->done) {
+                absorb<A_K>(pdir, b, A_MAXMASK, red, tot);
+                fin_direction(*s, tot);
+                if (threadIdx.x == 0 && !s->done) s->b_phase = 1;
+            }
+            state_publish(Sout, b, blk, s);
+        }
+    }
+    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&)[K]) const {
+        const Scal& s = *lc.sc;
         const T inv = (T)(1.0 / s.pnorm);
         const bool need_phi = LAST || (s.omega != 0.0 && AX < 2);
 #pragma unroll
@@ -424,7 +510,7 @@ struct OpLp {
     }
     __device__ void spectral(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K],
                              C2<T>* buf, const C2<T>* tw) const {
-        const Scal& s = S[lc.b];
+        const Scal& s = *lc.sc;
         const double rot = rot_coef_s<AX>(s, lc);
         const double invM = 1.0 / lc.M;
         if (AX < 2 && s.omega != 0.0 && s.dim >= 2) {
@@ -476,36 +562,22 @@ struct OpLp {
             }
         }
     }
-    __device__ void finalize(const Geo&, int b, const double* t) const {
-        __shared__ double tot[B_K];
-        __shared__ double part_out[B_K];
-        __shared__ double scratch[(512 / 64) * B_K];
-        for (int k = threadIdx.x; k < B_K; k += blockDim.x) tot[k] = t[k];
-        __syncthreads();
-        auto merge = [&](const Partials P) {
-            if (!P.parts) return;
-            reduce_partials<B_K>(P.parts + (size_t)b * P.nb * B_K, P.nb, scratch, part_out, B_MAXMASK);
-            for (int k = threadIdx.x; k < B_K; k += blockDim.x) {
-                const bool mx = (B_MAXMASK >> k) & 1u;
-                tot[k] = mx ? fmax(tot[k], part_out[k]) : tot[k] + part_out[k];
-            }
-            __syncthreads();
-        };
-        merge(prev0);
-        merge(prev1);
-        fin_step(S[b], tot);
-    }
 };
 
-// Diagonal preconditioners (identity, P_V): residual, P r and all phase-A sums in one sweep.
+// ---------------------------------------------------------------------------------------------
+// Diagonal preconditioners (identity, P_V): [step], the pending retraction, residual, P r and all
+// phase-A sums in one pointwise sweep (fixed chunks per block: deterministic partials).
+// ---------------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, Scal* S, int64_t N, int nbpi, int pre,
-                                                   Partials pr) {
-    __shared__ double red[(256 / 64 + 1) * A_K + 8];
-    __shared__ int flag;
+__global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, const Scal* Sin, Scal* Sout, int64_t N, int nbpi,
+                                                   int pre, Partials pb0, Partials pb1, Partials pb2, Partials pr) {
+    __shared__ double red[(256 / 64 + 1) * 16 + 8];
+    __shared__ Scal s;
     const int b = blockIdx.x / nbpi;
     const int blk = blockIdx.x - b * nbpi;
-    Scal& s = S[b];
+    state_load(Sin, b, blk, &s);
+    if (!s.done && s.b_phase) absorb_step(pb0, pb1, pb2, b, red, &s);
+    state_publish(Sout, b, blk, &s);
     if (s.done) return;
     double acc[A_K];
 #pragma unroll
@@ -522,20 +594,15 @@ __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, Scal* S, in
         const T rho = abs2(ph);
         const C2<T> r = add(lph, scl(ph, beta * rho - lam));
         f.r[i] = r;
-        const C2<T> pr = scl(r, pscale<T>(pre, pv_diag(s, (double)f.V[i], (double)rho)));
-        f.pr[i] = pr;
+        const C2<T> prv = scl(r, pscale<T>(pre, pv_diag(s, (double)f.V[i], (double)rho)));
+        f.pr[i] = prv;
         res_sums<T>(acc, r);
-        cg_sums<T>(acc, r, pr, f.rp[i], f.pp[i], ph);
+        cg_sums<T>(acc, r, prv, f.rp[i], f.pp[i], ph);
     }
     __shared__ double totals[A_K];
     block_reduce<A_K>(acc, red, totals, A_MAXMASK);
     double* P = pr.parts + ((size_t)b * nbpi + blk) * A_K;
     for (int k = threadIdx.x; k < A_K; k += blockDim.x) P[k] = totals[k];
-    if (last_block(pr.counters + b, (unsigned)nbpi, &flag)) {
-        reduce_partials<A_K>(pr.parts + (size_t)b * nbpi * A_K, nbpi, red, totals, A_MAXMASK);
-        fin_residual(s, totals);
-        fin_direction(s, totals);
-    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -547,13 +614,15 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     const bool f64 = sizeof(T) == 8;
     const int cb = (int)sizeof(C2<T>);
     const IterFields<T>& f = c.f;
+    Scal* S_step = c.S;
+    Scal* S_res = c.S + c.B;
+    Scal* S_dir = c.S + 2 * c.B;
     hipError_t e;
-    auto parts = [&](int region, int K, int ax) {
+    auto region = [&](int r, int ax) {
         Partials p;
-        p.parts = c.parts + (size_t)region * c.region_doubles;
-        p.counters = c.counters + (size_t)region * c.B;
+        p.parts = c.parts + (size_t)r * c.region_doubles;
+        p.counters = nullptr;
         p.nb = pass_blocks_per_field(g, ax, cb, c.B);
-        (void)K;
         return p;
     };
     const Partials none{nullptr, nullptr, 0};
@@ -562,8 +631,10 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     auto tick = [&](const char* name, double reals) {
         if (c.timer) c.timer->mark(s, name, reals * unit);
     };
-    const bool rot = g.dim >= 2;  // the B passes along x and y also read phi when omega != 0
-    (void)rot;
+    // partial regions of the direction passes (absorbed by the step at the next iteration's start)
+    const Partials pb0 = region(R_B0, 0);
+    const Partials pb1 = g.dim >= 2 ? region(R_B1, 1) : none;
+    const Partials pb2 = g.dim >= 3 ? region(R_B2, 2) : none;
     // ---- phase A ----
     int pre = 0, post = 0;
     const bool spectral_p = c.precond == GPE_P_KINETIC || c.precond == GPE_P_COMBINED || c.precond == GPE_P_C1 ||
@@ -571,66 +642,76 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     if (c.precond == GPE_P_COMBINED) pre = post = 1;
     if (c.precond == GPE_P_C1) post = 2;
     if (c.precond == GPE_P_C2 || c.precond == GPE_P_POTENTIAL) pre = 2;
+    Partials pres = none, pdir;
+    const Scal* dir_in;
     if (!spectral_p) {
-        // diagonal P (identity or P_V): pointwise residual + P r + reductions in one kernel
+        // diagonal P (identity or P_V): one pointwise kernel for residual, P r and every sum
         const int nbpi = c.pointwise_blocks;
-        Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, c.counters + (size_t)R_A1 * c.B, nbpi};
+        Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, nullptr, nbpi};
         tick("step_resid_diag", 21);
-        hipLaunchKernelGGL(k_resid_diag<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f, c.S, g.N, nbpi, pre,
-                           pr);
+        hipLaunchKernelGGL(k_resid_diag<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f, S_dir, S_step, g.N, nbpi,
+                           pre, pb0, pb1, pb2, pr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        pres = pr;
+        pdir = pr;
+        dir_in = S_step;
     } else if (g.dim == 1) {
-        OpResid<T, true> op{f, c.S, pre, post};
+        OpResid<T, true> op{f, S_dir, S_step, pb0, pb1, pb2, pre, post};
         tick("step_resid_precond_x", 21);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, parts(R_A1, A_K, 0), s)) != hipSuccess) return e;
+        const Partials pa = region(R_A1, 0);
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa, s)) != hipSuccess) return e;
+        pres = pa;
+        pdir = pa;
+        dir_in = S_step;
     } else {
-        OpResid<T, false> op{f, c.S, pre, post};
+        OpResid<T, false> op{f, S_dir, S_step, pb0, pb1, pb2, pre, post};
         tick("step_resid_fwd_x", 17);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, parts(R_A1, A_K, 0), s)) != hipSuccess) return e;
+        const Partials pa1 = region(R_A1, 0);
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa1, s)) != hipSuccess) return e;
         if (g.dim == 2) {
-            OpPMid<T, 1, true, true> y{f.w, c.S};
-            tick("precond_y", 4);
+            OpPMid<T, 1, true, true, true> y{f.w, S_step, S_res, pa1};
+            tick("resid_test_precond_y", 4);
             if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y, none, s)) != hipSuccess) return e;
         } else {
-            OpPMid<T, 1, true, false> y1{f.w, c.S};
-            tick("precond_fwd_y", 4);
+            OpPMid<T, 1, true, false, true> y1{f.w, S_step, S_res, pa1};
+            tick("resid_test_precond_fwd_y", 4);
             if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y1, none, s)) != hipSuccess) return e;
-            OpPMid<T, 2, true, true> z{f.w, c.S};
+            OpPMid<T, 2, true, true, false> z{f.w, S_res, nullptr, none};
             tick("precond_z", 4);
             if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), z, none, s)) != hipSuccess) return e;
-            OpPMid<T, 1, false, true> y2{f.w, c.S};
+            OpPMid<T, 1, false, true, false> y2{f.w, S_res, nullptr, none};
             tick("precond_inv_y", 4);
             if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y2, none, s)) != hipSuccess) return e;
         }
-        OpPLast<T> op3{f, c.S, post};
+        OpPLast<T> op3{f, S_res, post};
         tick("precond_inv_x", 13);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op3, parts(R_A3, A_K, 0), s)) != hipSuccess) return e;
+        const Partials pa3 = region(R_A3, 0);
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op3, pa3, s)) != hipSuccess) return e;
+        pdir = pa3;
+        dir_in = S_res;
     }
     // ---- phase B ----
     if (g.dim == 1) {
-        OpLp<T, 0, true, true> op{f, c.S, none, none};
-        tick("dir_Lp_x", 11);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, parts(R_B0, B_K, 0), s)) != hipSuccess) return e;
+        OpLp<T, 0, true, true> op{f, dir_in, S_dir, pres, pdir};
+        tick("dir_Lp_x_linesearch", 11);
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pb0, s)) != hipSuccess) return e;
     } else if (g.dim == 2) {
-        OpLp<T, 0, true, false> ox{f, c.S, none, none};
-        Partials p0 = parts(R_B0, B_K, 0);
+        OpLp<T, 0, true, false> ox{f, dir_in, S_dir, pres, pdir};
         tick("dir_Lp_x", 10);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, p0, s)) != hipSuccess) return e;
-        OpLp<T, 1, false, true> oy{f, c.S, p0, none};
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, pb0, s)) != hipSuccess) return e;
+        OpLp<T, 1, false, true> oy{f, S_dir, nullptr, none, none};
         tick("Lp_y_linesearch", 9);
-        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, parts(R_B1, B_K, 1), s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, pb1, s)) != hipSuccess) return e;
     } else {
-        OpLp<T, 0, true, false> ox{f, c.S, none, none};
-        Partials p0 = parts(R_B0, B_K, 0);
+        OpLp<T, 0, true, false> ox{f, dir_in, S_dir, pres, pdir};
         tick("dir_Lp_x", 10);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, p0, s)) != hipSuccess) return e;
-        OpLp<T, 1, false, false> oy{f, c.S, none, none};
-        Partials p1 = parts(R_B1, B_K, 1);
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, pb0, s)) != hipSuccess) return e;
+        OpLp<T, 1, false, false> oy{f, S_dir, nullptr, none, none};
         tick("Lp_y", 8);
-        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, p1, s)) != hipSuccess) return e;
-        OpLp<T, 2, false, true> oz{f, c.S, p0, p1};
+        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, pb1, s)) != hipSuccess) return e;
+        OpLp<T, 2, false, true> oz{f, S_dir, nullptr, none, none};
         tick("Lp_z_linesearch", 9);
-        if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), oz, parts(R_B2, B_K, 2), s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), oz, pb2, s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

@@ -215,8 +215,13 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
     const int64_t N = g.N;
     hipError_t e;
     // scalars to the device
-    if ((e = hipMemcpyAsync(pa.S, host_S.data(), sizeof(Scal) * B, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
-    if ((e = normalize_all<T>(f, B, N, pa.S, *pa.red, s)) != hipSuccess) return e;
+    // three versioned state slots (after the step, after the convergence test, after the direction);
+    // an iteration starts from S_dir
+    Scal* S_dir = pa.S + 2 * B;
+    for (int k = 0; k < 3; ++k)
+        if ((e = hipMemcpyAsync(pa.S + k * B, host_S.data(), sizeof(Scal) * B, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return e;
+    if ((e = normalize_all<T>(f, B, N, S_dir, *pa.red, s)) != hipSuccess) return e;
     if ((e = zero_cg_memory<T>(f, (int64_t)B * N, s)) != hipSuccess) return e;
     for (int b = 0; b < B; ++b) {
         Geo gb = g;
@@ -225,7 +230,7 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
             gb.h[a] = host_S[b].h[a];
         }
         gb.cell = host_S[b].cell;
-        if ((e = refresh_instance<T>(gb, *pa.tw, f, (int64_t)b * N, pa.S + b, host_S[b].beta, host_S[b].omega,
+        if ((e = refresh_instance<T>(gb, *pa.tw, f, (int64_t)b * N, S_dir + b, host_S[b].beta, host_S[b].omega,
                                      *pa.red, true, s)) != hipSuccess)
             return e;
     }
@@ -253,7 +258,7 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
             std::swap(c.f.r, c.f.rp);
         }
         since_refresh += pa.check_every;
-        if ((e = hipMemcpyAsync(host_S.data(), pa.S, sizeof(Scal) * B, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        if ((e = hipMemcpyAsync(host_S.data(), S_dir, sizeof(Scal) * B, hipMemcpyDeviceToHost, s)) != hipSuccess)
             return e;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
         bool all_done = true;
@@ -270,7 +275,7 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
                     gb.h[a] = host_S[b].h[a];
                 }
                 gb.cell = host_S[b].cell;
-                if ((e = refresh_instance<T>(gb, *pa.tw, c.f, (int64_t)b * N, pa.S + b, host_S[b].beta,
+                if ((e = refresh_instance<T>(gb, *pa.tw, c.f, (int64_t)b * N, S_dir + b, host_S[b].beta,
                                              host_S[b].omega, *pa.red, false, s)) != hipSuccess)
                     return e;
             }
@@ -288,13 +293,16 @@ hipError_t profile_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host
     const Geo& g = pa.g;
     const int64_t N = g.N;
     hipError_t e;
-    if ((e = hipMemcpyAsync(pa.S, host_S.data(), sizeof(Scal) * pa.B, hipMemcpyHostToDevice, s)) != hipSuccess)
-        return e;
-    if ((e = normalize_all<T>(f, pa.B, N, pa.S, *pa.red, s)) != hipSuccess) return e;
+    Scal* S_dir = pa.S + 2 * pa.B;
+    for (int k = 0; k < 3; ++k)
+        if ((e = hipMemcpyAsync(pa.S + k * pa.B, host_S.data(), sizeof(Scal) * pa.B, hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return e;
+    if ((e = normalize_all<T>(f, pa.B, N, S_dir, *pa.red, s)) != hipSuccess) return e;
     if ((e = zero_cg_memory<T>(f, (int64_t)pa.B * N, s)) != hipSuccess) return e;
     for (int b = 0; b < pa.B; ++b) {
-        if ((e = refresh_instance<T>(g, *pa.tw, f, (int64_t)b * N, pa.S + b, host_S[b].beta, host_S[b].omega, *pa.red,
-                                     true, s)) != hipSuccess)
+        if ((e = refresh_instance<T>(g, *pa.tw, f, (int64_t)b * N, S_dir + b, host_S[b].beta, host_S[b].omega,
+                                     *pa.red, true, s)) != hipSuccess)
             return e;
     }
     IterCtx<T> c;
@@ -314,7 +322,7 @@ hipError_t profile_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host
         if ((e = timer.collect(s)) != hipSuccess) return e;
         std::swap(c.f.r, c.f.rp);
     }
-    return hipMemcpy(host_S.data(), pa.S, sizeof(Scal) * pa.B, hipMemcpyDeviceToHost);
+    return hipMemcpy(host_S.data(), S_dir, sizeof(Scal) * pa.B, hipMemcpyDeviceToHost);
 }
 
 template hipError_t profile_phase<double>(PhaseArgs&, IterFields<double>, std::vector<Scal>&, int, KernelTimer&,
