@@ -8,9 +8,9 @@
 namespace gpe {
 
 constexpr size_t kPassLdsBudget = 96 * 1024;
-// Workgroup size cap of the passes: 512 threads lets every kernel keep up to 256 VGPRs per lane
-// (no scratch spills); x passes use at most 256 threads.
-constexpr int kMaxPassThreads = 512;
+// Workgroup size cap of the passes: with 256 threads (one wave per SIMD) every kernel may keep up
+// to 256 VGPRs per lane without scratch spills.
+constexpr int kMaxPassThreads = 256;
 
 inline size_t pass_lds_bytes_cb(int cb, int M, int C, int threads, int K) {
     size_t b = (size_t)cb * ((size_t)M + (size_t)C * line_stride(M));
@@ -31,13 +31,14 @@ inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes, int B =
     int C;
     if (AX == 0) {
         C = std::max(1, 256 / TPL);
-        while (C > 1 && lines / C < 1024) C >>= 1;
     } else {
         C = std::max(1, 128 / complex_bytes);
-        C = std::min(C, std::max(1, kMaxPassThreads / TPL));
+        C = std::min(C, std::max(1, 256 / TPL));
         C = std::min(C, g.n[0]);
-        while (C > 2 && lines / C < 512) C >>= 1;
     }
+    // keep at least 64 workgroups so that small grids still spread over the chip; larger groups
+    // keep the per-instance partial rows (which every consumer workgroup reduces) few
+    while (C > 1 && lines / C < 64) C >>= 1;
     while (C > 1 && (lpf % C) != 0) C >>= 1;
     // keep the LDS footprint (twiddles + lines + reduction scratch) within budget
     while (C > 1 && pass_lds_bytes_cb(complex_bytes, g.n[AX], C, C * TPL, 32) > kPassLdsBudget) C >>= 1;
@@ -59,14 +60,14 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
     pr.nb = nb;
     // reduction scratch sized for the pass's own sums and for absorbing up to 16 sums of its predecessor
     const size_t lds = pass_lds_bytes<T>(g.n[AX], C, threads, Op::K > 16 ? Op::K : 16);
-    auto kern = threads <= 256 ? pass_kernel<T, AX, Op, 256> : pass_kernel<T, AX, Op, kMaxPassThreads>;
+    if (threads > kMaxPassThreads) return hipErrorInvalidConfiguration;
+    auto kern = pass_kernel<T, AX, Op, kMaxPassThreads>;
     static bool attr_set = false;  // one attribute call per instantiation
     if (!attr_set) {
         // Raise the dynamic-LDS cap once; a runtime that does not need it may refuse harmlessly.
-        for (auto k : {pass_kernel<T, AX, Op, 256>, pass_kernel<T, AX, Op, kMaxPassThreads>})
-            if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPassLdsBudget) !=
-                hipSuccess)
-                (void)hipGetLastError();
+        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPassLdsBudget) !=
+            hipSuccess)
+            (void)hipGetLastError();
         attr_set = true;
     }
     hipLaunchKernelGGL(kern, dim3((unsigned)(nb * (int64_t)B)), dim3(threads), lds, s, g, C,

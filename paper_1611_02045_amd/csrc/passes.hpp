@@ -116,7 +116,9 @@ __device__ __forceinline__ void reduce_partials(const double* parts, int nb, dou
 // The pass kernel.  Op must provide:
 //   static constexpr bool FWD, INV;  static constexpr int K;  static constexpr unsigned MAXMASK;
 //   static constexpr bool SCALARS;   (bit k of MAXMASK set: sum k is a max-reduction)
+//   static constexpr bool PREFETCH;
 //   struct State;
+//   __device__ void prefetch(const Geo&, const LineCtx&, State&) const;                   // if PREFETCH
 //   __device__ void begin(const Geo&, int b, int blk_in_inst, double* red, Scal* s) const;  // if SCALARS
 //   __device__ void load(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
 //   __device__ void spectral(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K],
@@ -135,6 +137,10 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
     double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem_raw) + off);
     const int blk_in_inst = pr.nb > 0 ? (int)(blockIdx.x % (unsigned)pr.nb) : 0;
     lc.sc = nullptr;
+    typename Op::State st;
+    // loads that do not depend on the scalar state are issued first, so that their latency
+    // overlaps the reduction of the previous pass's partials in begin()
+    if constexpr (Op::PREFETCH) op.prefetch(g, lc, st);
     if constexpr (Op::SCALARS) {
         __shared__ Scal s_local;
         op.begin(g, lc.b, blk_in_inst, red, &s_local);  // all threads; ends with a barrier
@@ -143,7 +149,6 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
     }
     load_twiddles(tw, twg, lc.M);
 
-    typename Op::State st;
     C2<T> v[8];
     double acc[Op::K > 0 ? Op::K : 1];
 #pragma unroll

@@ -292,7 +292,7 @@ __device__ void absorb_step(const Partials& p0, const Partials& p1, const Partia
 // ---------------------------------------------------------------------------------------------
 template <typename T, bool ONE>
 struct OpResid {
-    static constexpr bool FWD = true, INV = ONE, SCALARS = true;
+    static constexpr bool FWD = true, INV = ONE, SCALARS = true, PREFETCH = true;
     static constexpr int K = A_K;
     static constexpr unsigned MAXMASK = A_MAXMASK;
     IterFields<T> f;
@@ -301,10 +301,22 @@ struct OpResid {
     Partials pb0, pb1, pb2;
     int pre, post;
     struct State {
-        C2<T> ph[ONE ? 8 : 1];
+        C2<T> ph[8], lph[8], pp[8], lp[8];
+        T V[8];
         C2<T> r[ONE ? 8 : 1];
         double d[ONE ? 8 : 1];
     };
+    __device__ void prefetch(const Geo&, const LineCtx& lc, State& st) const {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = lc.at(q);
+            st.ph[q] = f.phi[i];
+            st.lph[q] = f.Lphi[i];
+            st.pp[q] = f.pp[i];
+            st.lp[q] = f.lp[i];
+            st.V[q] = f.V[i];
+        }
+    }
     __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s) const {
         state_load(Sin, b, blk, s);
         if (!s->done && s->b_phase) absorb_step(pb0, pb1, pb2, b, red, s);
@@ -316,10 +328,10 @@ struct OpResid {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
-            C2<T> ph = f.phi[i];
-            C2<T> lp = f.Lphi[i];
-            apply_step<T>(f, s, i, ph, lp, acc);
-            const T V = f.V[i];
+            C2<T> ph = st.ph[q];
+            C2<T> lp = st.lph[q];
+            apply_step_pref<T>(f, s, i, ph, lp, st.pp[q], st.lp[q], acc);
+            const T V = st.V[q];
             const T rho = abs2(ph);
             const C2<T> r = add(lp, scl(ph, beta * rho - lam));
             f.r[i] = r;
@@ -368,14 +380,20 @@ struct OpResid {
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX, bool F, bool I, bool ABS>
 struct OpPMid {
-    static constexpr bool FWD = F, INV = I, SCALARS = true;
+    static constexpr bool FWD = F, INV = I, SCALARS = true, PREFETCH = true;
     static constexpr int K = 0;
     static constexpr unsigned MAXMASK = 0;
     C2<T>* w;
     const Scal* Sin;  // ABS: S_step; otherwise S_res
     Scal* Sout;       // ABS: S_res
     Partials pa1;
-    struct State {};
+    struct State {
+        C2<T> w[8];
+    };
+    __device__ void prefetch(const Geo&, const LineCtx& lc, State& st) const {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) st.w[q] = w[lc.at(q)];
+    }
     __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s) const {
         state_load(Sin, b, blk, s);
         if constexpr (ABS) {
@@ -387,9 +405,9 @@ struct OpPMid {
             state_publish(Sout, b, blk, s);
         }
     }
-    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1]) const {
+    __device__ void load(const Geo&, const LineCtx&, State& st, C2<T> (&v)[8], double (&)[1]) const {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = w[lc.at(q)];
+        for (int q = 0; q < 8; ++q) v[q] = st.w[q];
     }
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
                              const C2<T>*) const {
@@ -423,7 +441,7 @@ struct OpPMid {
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 struct OpPLast {
-    static constexpr bool FWD = false, INV = true, SCALARS = true;
+    static constexpr bool FWD = false, INV = true, SCALARS = true, PREFETCH = false;
     static constexpr int K = A_K;
     static constexpr unsigned MAXMASK = A_MAXMASK;
     IterFields<T> f;
@@ -460,7 +478,7 @@ struct OpPLast {
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX, bool FIRST, bool LAST>
 struct OpLp {
-    static constexpr bool FWD = true, INV = true, SCALARS = true;
+    static constexpr bool FWD = true, INV = true, SCALARS = true, PREFETCH = FIRST;
     static constexpr int K = B_K;
     static constexpr unsigned MAXMASK = B_MAXMASK;
     IterFields<T> f;
@@ -472,6 +490,15 @@ struct OpLp {
         C2<T> ph[8];
         C2<T> p[8];
     };
+    // FIRST: phi and the preconditioned residual P r (into p, where load() builds the new direction)
+    __device__ void prefetch(const Geo&, const LineCtx& lc, State& st) const {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = lc.at(q);
+            st.ph[q] = f.phi[i];
+            st.p[q] = f.pr[i];
+        }
+    }
     __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s) const {
         state_load(Sin, b, blk, s);
         if constexpr (FIRST) {
@@ -497,10 +524,9 @@ struct OpLp {
             const int64_t i = lc.at(q);
             C2<T> p;
             if constexpr (FIRST) {
-                const C2<T> ph = f.phi[i];
-                p = sub(scl(f.pp[i], (T)s.beta_cg), add(f.pr[i], scl(ph, (T)s.rho)));
+                const C2<T> ph = st.ph[q];
+                p = sub(scl(f.pp[i], (T)s.beta_cg), add(st.p[q], scl(ph, (T)s.rho)));
                 f.pp[i] = p;
-                st.ph[q] = ph;
             } else {
                 p = f.pp[i];
                 if (need_phi) st.ph[q] = f.phi[i];
@@ -606,6 +632,19 @@ __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, const Scal*
 }
 
 // ---------------------------------------------------------------------------------------------
+// Collapse the per-block partial rows of each instance into one row (one workgroup per instance,
+// fixed order), so that the consuming pass's workgroups reduce a single row.
+// ---------------------------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(256) void k_collapse(const double* parts, int nb, double* out, unsigned mask) {
+    __shared__ double red[(256 / 64) * K];
+    __shared__ double tot[K];
+    const int b = blockIdx.x;
+    reduce_partials<K>(parts + (size_t)b * nb * K, nb, red, tot, mask);
+    for (int k = threadIdx.x; k < K; k += blockDim.x) out[(size_t)b * K + k] = tot[k];
+}
+
+// ---------------------------------------------------------------------------------------------
 // Host: enqueue one iteration for B instances.
 // ---------------------------------------------------------------------------------------------
 template <typename T>
@@ -625,16 +664,32 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         p.nb = pass_blocks_per_field(g, ax, cb, c.B);
         return p;
     };
+    // the view a consumer absorbs: the region itself, or its one-row collapse for many rows
+    auto consumable = [&](const Partials& p, int rc, int K, unsigned mask) -> Partials {
+        if (p.nb <= kAbsorbRows) return p;
+        Partials q{c.parts + (size_t)rc * c.region_doubles, nullptr, 1};
+        if (K == A_K)
+            hipLaunchKernelGGL(k_collapse<A_K>, dim3((unsigned)c.B), dim3(256), 0, s, p.parts, p.nb, q.parts, mask);
+        else
+            hipLaunchKernelGGL(k_collapse<B_K>, dim3((unsigned)c.B), dim3(256), 0, s, p.parts, p.nb, q.parts, mask);
+        return q;
+    };
     const Partials none{nullptr, nullptr, 0};
     // algorithmic bytes of a launch: `reals` real numbers of sizeof(T) per grid point and instance
     const double unit = (double)sizeof(T) * (double)g.N * (double)c.B;
     auto tick = [&](const char* name, double reals) {
         if (c.timer) c.timer->mark(s, name, reals * unit);
     };
-    // partial regions of the direction passes (absorbed by the step at the next iteration's start)
+    // partial regions of the direction passes (absorbed by the step at the next iteration's start,
+    // through their collapsed rows when they have many)
     const Partials pb0 = region(R_B0, 0);
     const Partials pb1 = g.dim >= 2 ? region(R_B1, 1) : none;
     const Partials pb2 = g.dim >= 3 ? region(R_B2, 2) : none;
+    auto view = [&](const Partials& p, int rc) -> Partials {
+        if (!p.parts || p.nb <= kAbsorbRows) return p;
+        return Partials{c.parts + (size_t)rc * c.region_doubles, nullptr, 1};
+    };
+    const Partials sb0 = view(pb0, R_B0C), sb1 = view(pb1, R_B1C), sb2 = view(pb2, R_B2C);
     // ---- phase A ----
     int pre = 0, post = 0;
     const bool spectral_p = c.precond == GPE_P_KINETIC || c.precond == GPE_P_COMBINED || c.precond == GPE_P_C1 ||
@@ -650,24 +705,25 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, nullptr, nbpi};
         tick("step_resid_diag", 21);
         hipLaunchKernelGGL(k_resid_diag<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f, S_dir, S_step, g.N, nbpi,
-                           pre, pb0, pb1, pb2, pr);
+                           pre, sb0, sb1, sb2, pr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        pres = pr;
-        pdir = pr;
+        pres = consumable(pr, R_A1C, A_K, A_MAXMASK);
+        pdir = pres;
         dir_in = S_step;
     } else if (g.dim == 1) {
-        OpResid<T, true> op{f, S_dir, S_step, pb0, pb1, pb2, pre, post};
+        OpResid<T, true> op{f, S_dir, S_step, sb0, sb1, sb2, pre, post};
         tick("step_resid_precond_x", 21);
         const Partials pa = region(R_A1, 0);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa, s)) != hipSuccess) return e;
-        pres = pa;
-        pdir = pa;
+        pres = consumable(pa, R_A1C, A_K, A_MAXMASK);
+        pdir = pres;
         dir_in = S_step;
     } else {
-        OpResid<T, false> op{f, S_dir, S_step, pb0, pb1, pb2, pre, post};
+        OpResid<T, false> op{f, S_dir, S_step, sb0, sb1, sb2, pre, post};
         tick("step_resid_fwd_x", 17);
-        const Partials pa1 = region(R_A1, 0);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa1, s)) != hipSuccess) return e;
+        const Partials pa1r = region(R_A1, 0);
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa1r, s)) != hipSuccess) return e;
+        const Partials pa1 = consumable(pa1r, R_A1C, A_K, A_MAXMASK);
         if (g.dim == 2) {
             OpPMid<T, 1, true, true, true> y{f.w, S_step, S_res, pa1};
             tick("resid_test_precond_y", 4);
@@ -687,7 +743,7 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         tick("precond_inv_x", 13);
         const Partials pa3 = region(R_A3, 0);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op3, pa3, s)) != hipSuccess) return e;
-        pdir = pa3;
+        pdir = consumable(pa3, R_A3C, A_K, A_MAXMASK);
         dir_in = S_res;
     }
     // ---- phase B ----
@@ -713,7 +769,10 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         tick("Lp_z_linesearch", 9);
         if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), oz, pb2, s)) != hipSuccess) return e;
     }
-    return hipSuccess;
+    (void)consumable(pb0, R_B0C, B_K, B_MAXMASK);
+    if (pb1.parts) (void)consumable(pb1, R_B1C, B_K, B_MAXMASK);
+    if (pb2.parts) (void)consumable(pb2, R_B2C, B_K, B_MAXMASK);
+    return hipGetLastError();
 }
 
 template hipError_t enqueue_iteration<double>(const IterCtx<double>&, hipStream_t);

@@ -21,7 +21,12 @@ struct IterFields {
 };
 
 // Partial-sum regions (one per reducing kernel) and their ticket counters.
-enum : int { R_A1 = 0, R_A3 = 1, R_B0 = 2, R_B1 = 3, R_B2 = 4, R_C = 5, R_COUNT = 6 };
+// Partial-sum regions of the reducing passes, and their collapsed counterparts (one row per
+// instance) used when a pass has more workgroups per instance than a consumer should re-reduce.
+enum : int {
+    R_A1 = 0, R_A3, R_B0, R_B1, R_B2, R_A1C, R_A3C, R_B0C, R_B1C, R_B2C, R_COUNT
+};
+constexpr int kAbsorbRows = 256;
 
 // Optional per-kernel timing of an iteration with HIP events recorded on the iteration's stream
 // between consecutive launches (used by gpe_pcg_profile).
@@ -105,13 +110,14 @@ constexpr unsigned B_MAXMASK = 1u << B_NF;
 
 // Pending retraction step of the previous iteration, applied pointwise at the start of phase A:
 // phi <- c_phi phi + c_p p, L phi <- c_L L phi + c_Lp L phat (linearity of L), with the fresh
-// sums of the new iterate.  ph and lph hold the loaded values and receive the updated ones.
+// sums of the new iterate.  ph and lph hold the loaded values and receive the updated ones; pp and
+// lpv are p and L phat at the same point (read only when has_step).
 template <typename T>
-__device__ __forceinline__ void apply_step(const IterFields<T>& f, const Scal& s, int64_t i, C2<T>& ph, C2<T>& lph,
-                                           double* acc) {
+__device__ __forceinline__ void apply_step_pref(const IterFields<T>& f, const Scal& s, int64_t i, C2<T>& ph,
+                                                C2<T>& lph, C2<T> pp, C2<T> lpv, double* acc) {
     if (s.has_step) {
-        const C2<T> np = add(scl(ph, (T)s.c_phi), scl(f.pp[i], (T)s.c_p));
-        const C2<T> nl = add(scl(lph, (T)s.c_L), scl(f.lp[i], (T)s.c_Lp));
+        const C2<T> np = add(scl(ph, (T)s.c_phi), scl(pp, (T)s.c_p));
+        const C2<T> nl = add(scl(lph, (T)s.c_L), scl(lpv, (T)s.c_Lp));
         acc[A_DPHI] = fmax(acc[A_DPHI], sqrt((double)abs2(sub(np, ph))));
         f.phi[i] = np;
         f.Lphi[i] = nl;
@@ -122,6 +128,13 @@ __device__ __forceinline__ void apply_step(const IterFields<T>& f, const Scal& s
     acc[A_A] += (double)redot(ph, lph);
     acc[A_Q4] += r2 * r2;
     acc[A_N2] += r2;
+}
+
+// As apply_step_pref, loading p and L phat itself.
+template <typename T>
+__device__ __forceinline__ void apply_step(const IterFields<T>& f, const Scal& s, int64_t i, C2<T>& ph, C2<T>& lph,
+                                           double* acc) {
+    apply_step_pref<T>(f, s, i, ph, lph, s.has_step ? f.pp[i] : C2<T>{}, s.has_step ? f.lp[i] : C2<T>{}, acc);
 }
 
 template <typename T>

@@ -157,3 +157,35 @@ def test_nonfinite_input_is_reported(torch_gpu):
     with pytest.raises(gpe.GpeError) as ei:
         _gpu_solve(torch_gpu, prob, V, phi0)
     assert ei.value.status == -4
+
+
+def test_trajectory_large_grid_collapsed_partials(torch_gpu):
+    """1024^2 (512 partial rows per pass, reduced through the one-row collapse): the first
+    iterations agree with the oracle."""
+    prob = Problem(2, (1024, 1024), (16.0, 16.0), 500.0, 0.6)
+    V = harmonic_potential(prob)
+    phi0 = vortex_seed_2d(prob, 21)
+    print("trajectory 1024^2", flush=True)
+    ref = O.pcg(prob, V, phi0, tol_res=1e-30, max_iter=6, record=True)
+    rep, _, hist = _gpu_solve(torch_gpu, prob, V, phi0, tol_res=1e-30, max_iter=6, record_history=1,
+                              check_every=2)
+    assert rep["iters"] == 6
+    for h_ref, h in zip(ref.history, hist):
+        assert abs(h["E"] - h_ref["E"]) < 1e-11 * abs(h_ref["E"])
+        assert abs(h["res"] - h_ref["res"]) < 1e-8 * h_ref["res"]
+
+
+@pytest.mark.timeout(600)
+def test_3d_rotating_workload_mixed(torch_gpu):
+    """3-D 128^3 on [-8,8]^3, V = (x^2 + y^2 + 4 z^2)/2, beta = 5000, Omega = 0.8, mixed precision to
+    ||r||_inf <= 1e-8; the oracle re-evaluates the GPU state (energy and residual)."""
+    from gpe_inputs import workload_3d
+    prob, V, phi0 = workload_3d(128)
+    print("3d 128^3 mixed solve", flush=True)
+    rep, phi, _ = _gpu_solve(torch_gpu, prob, V, phi0, tol_res=1e-8, max_iter=100000, precision="mixed")
+    print(f"  iters {rep['iters']} (fp32 {rep['iters_fp32']}), E = {rep['E']:.10f}, {rep['seconds']:.2f} s", flush=True)
+    assert rep["status"] == 0 and rep["res_inf"] <= 1e-8
+    r, lam = O.residual(prob, V, phi)
+    assert float(np.max(np.abs(r))) <= 1.2e-8
+    assert abs(O.energy(prob, V, phi) - rep["E"]) < 1e-10 * abs(rep["E"])
+    assert abs(lam - rep["lam"]) < 1e-10 * abs(lam)
