@@ -56,7 +56,7 @@ __device__ __forceinline__ double coord_of(int k, double L, double h) { return -
 // ------------------------------------------------------------------------------------------------
 // Per-instance solver state (FP64).  One struct per instance, resident in device memory.
 // ------------------------------------------------------------------------------------------------
-struct Scal {
+struct alignas(16) Scal {
     // problem parameters (per instance: batched solves mix boxes, beta and omega)
     double beta, omega, cell;
     double L[3], h[3];
@@ -100,34 +100,76 @@ struct Scal {
 enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_LINESEARCH = -5, ST_NONFINITE = -4 };
 
 // ------------------------------------------------------------------------------------------------
-// Deterministic block reduction of K doubles: a masked xor-shuffle tree inside each wave (lanes
-// beyond the block's last thread contribute the identity), then the waves combined in a fixed
-// order.  Entry k is summed, or max-reduced when bit k of `maxmask` is set.  `red` is LDS scratch
-// of at least (blockDim/64) * K doubles; `out` is an LDS array of K doubles that holds the totals
-// for every thread on return.  Works for any block size; must be called by every thread.
+// Deterministic block reduction of K doubles.  Entry k is summed, or max-reduced when bit k of
+// `maxmask` is set.  Inside a full wave the K entries are reduced by a transposing butterfly: at
+// each of the first log2(K') exchanges (K' = K rounded up to a power of two) a lane keeps half of
+// its entries and trades the other half with its partner; after log2(64 / K') plain xor steps
+// lane l holds entry l / (64 / K') summed over the wave, for K' - 1 + log2(64 / K') exchanges in
+// total instead of 6 K.  Blocks whose size is not a multiple of 64 take a masked xor tree per entry (lanes beyond
+// the block's last thread contribute the identity).  The waves are then combined in a fixed order.
+// `red` is LDS scratch of at least (blockDim/64 + 1) * K doubles; `out` is an LDS array of K
+// doubles that holds the totals for every thread on return; v is clobbered.  Must be called by
+// every thread of the block, in uniform control flow.
 // ------------------------------------------------------------------------------------------------
+// One exchange of the transposing butterfly (HALF entries traded with the lane at distance OFF),
+// then the next; template recursion keeps every register index a compile-time constant.
+template <int HALF, int OFF, int KP>
+__device__ __forceinline__ void butterfly_round(double (&u)[KP], int lane, int& base, unsigned maxmask) {
+    if constexpr (HALF >= 1) {
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int j = 0; j < HALF; ++j) {
+            const double keep = up ? u[j + HALF] : u[j];
+            const double send = up ? u[j] : u[j + HALF];
+            const double recv = __shfl_xor(send, OFF, 64);
+            const bool mx = (maxmask >> (base + (up ? HALF : 0) + j)) & 1u;
+            u[j] = mx ? fmax(keep, recv) : keep + recv;
+        }
+        base += up ? HALF : 0;
+        butterfly_round<HALF / 2, OFF / 2, KP>(u, lane, base, maxmask);
+    }
+}
+
 template <int K>
 __device__ __forceinline__ void block_reduce(double (&v)[K], double* red, double* out, unsigned maxmask) {
+    static_assert(K >= 1 && K <= 64, "block_reduce handles 1..64 entries");
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
-    const int nact = min(64, (int)blockDim.x - wave * 64);
+    if ((blockDim.x & 63u) == 0) {
+        constexpr int KP = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : K <= 32 ? 32 : 64;
+        double u[KP];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = v[k];
-        const bool mx = (maxmask >> k) & 1u;
+        for (int k = 0; k < KP; ++k) u[k] = k < K ? v[k] : 0.0;  // padding entries are sums of zeros
+        int base = 0;  // first entry index still held by this lane
+        butterfly_round<KP / 2, 32>(u, lane, base, maxmask);
+        const bool mx = (maxmask >> base) & 1u;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            double o = __shfl_xor(s, off, 64);
-            if ((lane ^ off) >= nact) o = mx ? -1e300 : 0.0;
-            s = mx ? fmax(s, o) : s + o;
+        for (int off = 32 / KP; off >= 1; off >>= 1) {
+            const double o = __shfl_xor(u[0], off, 64);
+            u[0] = mx ? fmax(u[0], o) : u[0] + o;
         }
-        v[k] = s;
-    }
-    __syncthreads();
-    if (lane == 0) {
+        __syncthreads();
+        if ((lane & (64 / KP - 1)) == 0 && base < K) red[wave * K + base] = u[0];
+    } else {
+        const int nact = min(64, (int)blockDim.x - wave * 64);
 #pragma unroll
-        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+        for (int k = 0; k < K; ++k) {
+            double s = v[k];
+            const bool mx = (maxmask >> k) & 1u;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                double o = __shfl_xor(s, off, 64);
+                if ((lane ^ off) >= nact) o = mx ? -1e300 : 0.0;
+                s = mx ? fmax(s, o) : s + o;
+            }
+            v[k] = s;
+        }
+        __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += blockDim.x) {

@@ -58,6 +58,7 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
     const int threads = C * TPL;
     const int nb = (int)(lines_per_field(g, AX) / C);
     pr.nb = nb;
+    if (pr.stride == 0) pr.stride = nb;
     // reduction scratch sized for the pass's own sums and for absorbing up to 16 sums of its predecessor
     const size_t lds = pass_lds_bytes<T>(g.n[AX], C, threads, Op::K > 16 ? Op::K : 16);
     if (threads > kMaxPassThreads) return hipErrorInvalidConfiguration;

@@ -72,7 +72,7 @@ static hipError_t apply_t(const Geo& g, int B, const Twiddles& tw, const void* f
                           void* tmp, double beta, double omega, bool nl, hipStream_t s) {
     const bool f64 = sizeof(T) == 8;
     const C2<T>* F = (const C2<T>*)f;
-    Partials none{nullptr, nullptr, 0};
+    Partials none{nullptr, 0, 0, 0};
     hipError_t e;
     if (g.dim == 1) {
         OpApply<T, 0> op{F, nullptr, (C2<T>*)out, (const T*)V, beta, omega, 1, nl};
@@ -96,7 +96,7 @@ template <typename T>
 static hipError_t rotation_t(const Geo& g, const Twiddles& tw, const void* f, void* out, void* tmp, hipStream_t s) {
     const bool f64 = sizeof(T) == 8;
     const C2<T>* F = (const C2<T>*)f;
-    Partials none{nullptr, nullptr, 0};
+    Partials none{nullptr, 0, 0, 0};
     hipError_t e;
     OpApply<T, 0> ox{F, nullptr, (C2<T>*)tmp, nullptr, 0.0, 1.0, 0, 0, 0.0};
     if ((e = launch_pass<T, 0>(g, 1, tw.get(0, f64), ox, none, s)) != hipSuccess) return e;
@@ -190,7 +190,7 @@ static hipError_t energy_t(const Geo& g, const Twiddles& tw, const void* phi, co
     int nn[3] = {0, 0, 0};
     hipError_t e;
     for (int ax = 0; ax < g.dim; ++ax) {
-        Partials pr{parts + off, nullptr, 0};
+        Partials pr{parts + off, 0, 0, 0};
         const int nb = pass_blocks_per_field(g, ax, cb);
         if (ax == 0) e = launch_pass<T, 0>(g, 1, tw.get(0, f64), OpEnergy<T, 0>{P, (const T*)V, omega}, pr, s);
         else if (ax == 1) e = launch_pass<T, 1>(g, 1, tw.get(1, f64), OpEnergy<T, 1>{P, (const T*)V, omega}, pr, s);
@@ -302,7 +302,7 @@ static hipError_t kinetic_chain(const Geo& g, const Twiddles& tw, const C2<T>* r
                                 const C2<T>* phi, const T* V, const double* alpha, double beta, int pre,
                                 int post, hipStream_t s) {
     const bool f64 = sizeof(T) == 8;
-    Partials none{nullptr, nullptr, 0};
+    Partials none{nullptr, 0, 0, 0};
     hipError_t e;
     if (g.dim == 1) {
         OpPre<T, 0, true, true> op{r, out, phi, V, alpha, beta, pre, post};

@@ -39,40 +39,45 @@ __host__ __device__ inline int64_t lines_per_field(const Geo& g, int AX) {
     return g.N / g.n[AX];
 }
 
+// Every extent is a power of two, so the decomposition of the launch into lines uses shifts and
+// masks only (64-bit integer division is a long software sequence on the GPU).  blk receives the
+// workgroup's index within its instance.
 template <int AX>
-__device__ __forceinline__ LineCtx decode_line(const Geo& g, int C) {
+__device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
     LineCtx lc;
     lc.lg = g.lg[AX];
     lc.M = 1 << lc.lg;
     lc.TPL = lc.M >> 3;
+    const int lgC = __ffs(C) - 1;
     const int tid = threadIdx.x;
     if (AX == 0) {
         lc.c = tid >> (lc.lg - 3);
         lc.t = tid & (lc.TPL - 1);
     } else {
         lc.c = tid & (C - 1);
-        lc.t = tid / C;
+        lc.t = tid >> lgC;
     }
-    const int64_t line = (int64_t)blockIdx.x * C + lc.c;
-    const int64_t lpf = lines_per_field(g, AX);
-    lc.b = (int)(line / lpf);
-    const int64_t lf = line - (int64_t)lc.b * lpf;
+    const int lg_lpf = g.lg[0] + g.lg[1] + g.lg[2] - lc.lg;  // log2 of the lines per field
+    const int64_t line = ((int64_t)blockIdx.x << lgC) + lc.c;
+    lc.b = (int)(line >> lg_lpf);
+    const int64_t lf = line & (((int64_t)1 << lg_lpf) - 1);
+    blk = (int)(lf >> lgC);
     lc.off_b = (int64_t)lc.b * g.N;
     const int nx = g.n[0], ny = g.n[1];
     if (AX == 0) {
-        lc.i1 = (int)(lf % ny);
-        lc.i2 = (int)(lf / ny);
-        lc.base = lc.off_b + lf * nx;
+        lc.i1 = (int)(lf & (ny - 1));
+        lc.i2 = (int)(lf >> g.lg[1]);
+        lc.base = lc.off_b + (lf << g.lg[0]);
         lc.stride = 1;
     } else if (AX == 1) {
-        lc.i1 = (int)(lf % nx);
-        lc.i2 = (int)(lf / nx);
-        lc.base = lc.off_b + (int64_t)lc.i2 * nx * ny + lc.i1;
+        lc.i1 = (int)(lf & (nx - 1));
+        lc.i2 = (int)(lf >> g.lg[0]);
+        lc.base = lc.off_b + ((int64_t)lc.i2 << (g.lg[0] + g.lg[1])) + lc.i1;
         lc.stride = nx;
     } else {
-        lc.i1 = (int)(lf % nx);
-        lc.i2 = (int)(lf / nx);
-        lc.base = lc.off_b + (int64_t)lc.i2 * nx + lc.i1;
+        lc.i1 = (int)(lf & (nx - 1));
+        lc.i2 = (int)(lf >> g.lg[0]);
+        lc.base = lc.off_b + ((int64_t)lc.i2 << g.lg[0]) + lc.i1;
         lc.stride = (int64_t)nx * ny;
     }
     return lc;
@@ -89,10 +94,15 @@ __host__ __device__ inline size_t pass_lds_bytes(int M, int C, int threads, int 
 
 // Partial-sum buffers for reducing passes: parts[b][block][K] (FP64) and one ticket counter per
 // instance.  `nb` is the number of blocks per instance.
+// A region of per-block partial rows (K doubles each).  A producing pass writes its block blk of
+// instance b to row b * stride + off + blk (several passes can share a region, at different
+// offsets); a consumer reduces rows [b * stride, b * stride + nb).  stride 0 means nb.
 struct Partials {
     double* parts;
-    unsigned int* counters;
     int nb;
+    int stride;
+    int off;
+    __host__ __device__ int row_stride() const { return stride > 0 ? stride : nb; }
 };
 
 // Sum K partials of instance b over its nb blocks with all threads of the (last) block, in a
@@ -113,13 +123,28 @@ __device__ __forceinline__ void reduce_partials(const double* parts, int nb, dou
     block_reduce<K>(acc, red, out, maxmask);
 }
 
+// Loads a solver pass issues before everything else (state, partial rows of its producers).
+template <class Op, bool = Op::SCALARS>
+struct IntakeOf {
+    struct type {};
+};
+template <class Op>
+struct IntakeOf<Op, true> {
+    using type = typename Op::Intake;
+};
+
+// Twiddles per thread fetched into registers ahead of the scalar logic (more go straight to LDS).
+constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
+
 // The pass kernel.  Op must provide:
 //   static constexpr bool FWD, INV;  static constexpr int K;  static constexpr unsigned MAXMASK;
 //   static constexpr bool SCALARS;   (bit k of MAXMASK set: sum k is a max-reduction)
 //   static constexpr bool PREFETCH;
 //   struct State;
 //   __device__ void prefetch(const Geo&, const LineCtx&, State&) const;                   // if PREFETCH
-//   __device__ void begin(const Geo&, int b, int blk_in_inst, double* red, Scal* s) const;  // if SCALARS
+//   struct Intake;                                                                         // if SCALARS
+//   __device__ void intake(int b, Intake&) const;                                          // if SCALARS
+//   __device__ void begin(const Geo&, int b, int blk_in_inst, double* red, Scal* s, Intake&) const;  // if SCALARS
 //   __device__ void load(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
 //   __device__ void spectral(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K],
 //                            C2<T>* buf, const C2<T>* tw) const;   (buf/tw: to transform more lines)
@@ -129,25 +154,40 @@ template <typename T, int AX, class Op, int MAXT>
 __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op,
                                                     Partials pr) {
     extern __shared__ double4 smem_raw[];
-    LineCtx lc = decode_line<AX>(g, C);
+    int blk_in_inst;
+    LineCtx lc = decode_line<AX>(g, C, blk_in_inst);
     C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
     C2<T>* buf = tw + lc.M + (size_t)lc.c * line_stride(lc.M);
     size_t off = sizeof(C2<T>) * ((size_t)lc.M + (size_t)C * line_stride(lc.M));
     off = (off + 15) & ~(size_t)15;
     double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem_raw) + off);
-    const int blk_in_inst = pr.nb > 0 ? (int)(blockIdx.x % (unsigned)pr.nb) : 0;
     lc.sc = nullptr;
     typename Op::State st;
-    // loads that do not depend on the scalar state are issued first, so that their latency
-    // overlaps the reduction of the previous pass's partials in begin()
+    // The loads of the scalar state and of the producers' partial rows go first, then every load
+    // that does not depend on the state (twiddles, fields): all complete in one round trip, and
+    // begin() waits for the first group only (memory counters retire in issue order).
+    typename IntakeOf<Op>::type in;
+    if constexpr (Op::SCALARS) op.intake(lc.b, in);
+    // (four named registers rather than an array, which the compiler may demote to scratch)
+    auto tw_at = [&](int j) { return min((int)(threadIdx.x + j * blockDim.x), lc.M - 1); };
+    const C2<T> tw0 = twg[tw_at(0)], tw1 = twg[tw_at(1)], tw2 = twg[tw_at(2)], tw3 = twg[tw_at(3)];
     if constexpr (Op::PREFETCH) op.prefetch(g, lc, st);
     if constexpr (Op::SCALARS) {
         __shared__ Scal s_local;
-        op.begin(g, lc.b, blk_in_inst, red, &s_local);  // all threads; ends with a barrier
+        op.begin(g, lc.b, blk_in_inst, red, &s_local, in);  // all threads; ends with a barrier
         if (s_local.done) return;                       // uniform per block (one instance per block)
         lc.sc = &s_local;
     }
-    load_twiddles(tw, twg, lc.M);
+    auto tw_put = [&](int j, C2<T> x) {
+        const int i = threadIdx.x + j * blockDim.x;
+        if (i < lc.M) tw[i] = x;
+    };
+    tw_put(0, tw0);
+    tw_put(1, tw1);
+    tw_put(2, tw2);
+    tw_put(3, tw3);
+    for (int i = threadIdx.x + kTwiddleRegs * blockDim.x; i < lc.M; i += blockDim.x) tw[i] = twg[i];
+    __syncthreads();
 
     C2<T> v[8];
     double acc[Op::K > 0 ? Op::K : 1];
@@ -164,7 +204,7 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
         const int nw = (blockDim.x + 63) >> 6;
         double* outK = red + (size_t)nw * Op::K;
         block_reduce<Op::K>(acc, red, outK, Op::MAXMASK);
-        double* P = pr.parts + ((size_t)lc.b * pr.nb + blk_in_inst) * Op::K;
+        double* P = pr.parts + ((size_t)lc.b * pr.row_stride() + pr.off + blk_in_inst) * Op::K;
         for (int k = threadIdx.x; k < Op::K; k += blockDim.x) P[k] = outK[k];
     }
 }

@@ -42,9 +42,16 @@ __device__ __forceinline__ double pv_diag(const Scal& S, double V, double rho) {
     return S.lamt + V + S.beta * rho;
 }
 
+// Pointwise factor of the diagonal preconditioner: P_V^{1/2} (kind 1), P_V (kind 2) or 1, in the
+// field precision.
 template <typename T>
 __device__ __forceinline__ T pscale(int kind, double d) {
-    return kind == 1 ? (T)(1.0 / sqrt(d)) : kind == 2 ? (T)(1.0 / d) : (T)1;
+    if constexpr (sizeof(T) == 8) {
+        return kind == 1 ? rsqrt(d) : kind == 2 ? 1.0 / d : 1.0;
+    } else {
+        const float df = (float)d;
+        return kind == 1 ? rsqrtf(df) : kind == 2 ? 1.0f / df : 1.0f;
+    }
 }
 
 // Rotation coefficient of the directional symbol (see ops.hip) from per-instance geometry.
@@ -61,14 +68,14 @@ __device__ __forceinline__ void hist_row(Scal& S, int col, double v) {
 }
 
 // Convergence test at the top of iteration n (Section 5.3; reading: ||r_n||_inf <= tol).
-__device__ void fin_residual(Scal& S, const double* t) {
-    if (threadIdx.x == 0) {
-        const double res = t[A_RES], nonfinite = t[A_NF];
+__device__ __forceinline__ void fin_residual(Scal& S, const double* t) {
+    {
+        const double res = sqrt(t[A_RES]), nonfinite = t[A_NF];  // the sums hold squared maxima
         // fresh scalars of phi_n (the step of the previous iteration has just been applied)
         S.a = S.cell * t[A_A];
         S.q4 = S.cell * t[A_Q4];
         S.nrm2 = S.cell * t[A_N2];
-        S.dphi = t[A_DPHI];
+        S.dphi = sqrt(t[A_DPHI]);
         S.E = S.a + 0.5 * S.beta * S.q4;
         S.has_step = 0;
         S.res = res;
@@ -101,13 +108,12 @@ __device__ void fin_residual(Scal& S, const double* t) {
             }
         }
     }
-    __syncthreads();
 }
 
 // CG direction from the A-phase sums (Section 5.2, readings: beta_0 = 0, PR+ with the stored
 // denominator, restart when Re<r, p> >= 0).
-__device__ void fin_direction(Scal& S, const double* t) {
-    if (threadIdx.x == 0 && !S.done) {
+__device__ __forceinline__ void fin_direction(Scal& S, const double* t) {
+    if (!S.done) {
         const double w = S.cell;
         const double rPr = w * t[A_RPR], rpPr = w * t[A_RPPR], Prphi = w * t[A_PRPHI], PrPr = w * t[A_PRPR];
         const double Prpp = w * t[A_PRPP], rpp = w * t[A_RPP], ppphi = w * t[A_PPPHI], pppp = w * t[A_PPPP];
@@ -141,7 +147,6 @@ __device__ void fin_direction(Scal& S, const double* t) {
         hist_row(S, 5, beta);
         hist_row(S, 7, (double)S.restarted);
     }
-    __syncthreads();
 }
 
 // Energy change along the great circle, from the B-phase sums (see the file comment).
@@ -156,8 +161,8 @@ __device__ __forceinline__ double delta_energy(double c, double s, double a, dou
 
 // Step selection (Section 5.1 heuristic; readings: theta_opt = -E'(0)/E''(0) when E''(0) > 0,
 // else theta_default; clamp to (0, pi/2]; halve until E decreases, at most max_halvings times).
-__device__ void fin_step(Scal& S, const double* t) {
-    if (threadIdx.x == 0 && !S.done) {
+__device__ __forceinline__ void fin_step(Scal& S, const double* t) {
+    if (!S.done) {
         const double w = S.cell;
         const double cR = w * t[B_CR], aR = w * t[B_AR], bR = w * t[B_BR];
         const double cc = w * t[B_C], b = w * t[B_B];
@@ -170,15 +175,19 @@ __device__ void fin_step(Scal& S, const double* t) {
         const double d2 = 2.0 * (cc + beta * SAC + 2.0 * beta * SBB - S.lam);
         double th = d2 > 0.0 ? -d1 / d2 : S.theta_default;
         th = fmin(fmax(th, 0.0), 1.5707963267948966);
-        double acc_t = -1.0, dE = 0.0;
+        double acc_t = -1.0, dE = 0.0, c = 1.0, s = 0.0;
         int j = 0;
         for (; j <= S.max_halvings; ++j) {
             const double tj = th * ldexp(1.0, -j);
             if (!(tj > 0.0)) break;
-            const double e = delta_energy(cos(tj), sin(tj), S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
+            double sj, cj;
+            sincos(tj, &sj, &cj);
+            const double e = delta_energy(cj, sj, S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
             if (e < 0.0) {
                 acc_t = tj;
                 dE = e;
+                c = cj;
+                s = sj;
                 break;
             }
         }
@@ -198,7 +207,6 @@ __device__ void fin_step(Scal& S, const double* t) {
             }
             S.done = 1;
         } else {
-            const double c = cos(acc_t), s = sin(acc_t);
             const double n2 = c * c * S.nrm2 + 2.0 * c * s * SB + s * s * SC;
             const double nu = 1.0 / sqrt(n2);
             S.theta = acc_t;
@@ -230,59 +238,163 @@ __device__ void fin_step(Scal& S, const double* t) {
             if (S.precision == 1) S.iters_fp32 += 1;
         }
     }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------------------------
 // Scalar-state helpers for the passes
 // ---------------------------------------------------------------------------------------------
-// Copy the instance's state into LDS; only the publishing block keeps the history pointer.
-__device__ __forceinline__ void state_load(const Scal* in, int b, int blk, Scal* s) {
-    if (threadIdx.x == 0) {
-        *s = in[b];
-        if (blk != 0) s->hist = nullptr;
+// The state of instance b travels as 16-byte chunks, one per thread, so that a block fetches it
+// in one round trip.
+constexpr int kScalChunks = (int)(sizeof(Scal) / sizeof(uint4));
+static_assert(sizeof(Scal) % sizeof(uint4) == 0, "Scal is copied in 16-byte chunks");
+
+// The state of instance b, fetched by the first threads (one chunk each) at the start of a pass
+// and stored into LDS in begin().
+struct StateChunk {
+    uint4 ch;
+    __device__ __forceinline__ void issue(const Scal* in, int b) {
+        if (threadIdx.x < kScalChunks) ch = reinterpret_cast<const uint4*>(in + b)[threadIdx.x];
     }
-    __syncthreads();
-}
-
-__device__ __forceinline__ void state_publish(Scal* out, int b, int blk, const Scal* s) {
-    __syncthreads();
-    if (blk == 0 && threadIdx.x == 0) {
-        Scal c = *s;
-        c.hist = out[b].hist;  // keep the instance's history pointer
-        out[b] = c;
+    __device__ __forceinline__ void store(const Scal* in, int b, Scal* s) const {
+        uint4* dst = reinterpret_cast<uint4*>(s);
+        if (threadIdx.x < kScalChunks) dst[threadIdx.x] = ch;
+        for (int c = threadIdx.x + blockDim.x; c < kScalChunks; c += blockDim.x)  // blocks < 28 threads
+            dst[c] = reinterpret_cast<const uint4*>(in + b)[c];
     }
-}
+};
 
-// Totals of K sums of instance b over the producing pass's blocks (LDS `out`, K doubles).
-template <int K>
-__device__ __forceinline__ void absorb(const Partials& P, int b, unsigned mask, double* red, double* out) {
-    reduce_partials<K>(P.parts + (size_t)b * P.nb * K, P.nb, red, out, mask);
-}
-
-// The step: totals of the direction passes (x, y, z partial regions, B sums).
-__device__ void absorb_step(const Partials& p0, const Partials& p1, const Partials& p2, int b, double* red,
-                            Scal* s) {
-    __shared__ double tot[B_K];
-    __shared__ double part[B_K];
-    for (int k = threadIdx.x; k < B_K; k += blockDim.x) tot[k] = 0.0;
-    __syncthreads();
-    auto merge = [&](const Partials& P) {
-        if (!P.parts) return;
-        absorb<B_K>(P, b, B_MAXMASK, red, part);
-        for (int k = threadIdx.x; k < B_K; k += blockDim.x) {
-            const bool mx = (B_MAXMASK >> k) & 1u;
-            tot[k] = mx ? fmax(tot[k], part[k]) : tot[k] + part[k];
+// The partial rows (K <= 16 sums) of instance b in a region, fetched at the start of a pass in an
+// (entry, row group) layout: thread t reads entry k = t % 16 of rows t / 16 + j G (G = blockDim / 16,
+// j < NV) into registers.  reduce() folds them (and any rows beyond NV G), combines the four row
+// groups of each wave by two exchanges and the waves through LDS, in a fixed order.  Blocks that
+// are not whole waves fetch nothing early and reduce row by row.  Rows may be stale (a region
+// whose sums are not pending), never out of bounds.
+template <int K, int NV>
+struct RowFetch {
+    static_assert(K >= 1 && K <= 16, "up to 16 sums per row");
+    double v[NV];
+    __device__ __forceinline__ static bool fast() { return (blockDim.x & 63u) == 0; }
+    __device__ __forceinline__ void issue(const Partials& P, int b, unsigned mask) {
+        if (!fast() || !P.parts || P.nb <= 0) return;
+        const int k = threadIdx.x & 15, grp = threadIdx.x >> 4, G = blockDim.x >> 4;
+        const double id = ((mask >> k) & 1u) ? -1e300 : 0.0;
+        const double* rows = P.parts + (size_t)b * P.row_stride() * K;
+        const int kc = k < K ? k : K - 1;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int r = grp + j * G;
+            const double x = rows[(size_t)min(r, P.nb - 1) * K + kc];  // clamped: always in bounds
+            v[j] = (k < K && r < P.nb) ? x : id;
+        }
+    }
+    __device__ __forceinline__ void reduce(const Partials& P, int b, unsigned mask, double* red, double* tot) const {
+        if (!P.parts || P.nb <= 0) {
+            for (int k = threadIdx.x; k < K; k += blockDim.x) tot[k] = ((mask >> k) & 1u) ? -1e300 : 0.0;
+            __syncthreads();
+            return;
+        }
+        const double* rows = P.parts + (size_t)b * P.row_stride() * K;
+        if (!fast()) {
+            reduce_partials<K>(rows, P.nb, red, tot, mask);
+            return;
+        }
+        const int k = threadIdx.x & 15, grp = threadIdx.x >> 4, G = blockDim.x >> 4;
+        const bool mx = (mask >> k) & 1u;
+        double a = v[0];
+#pragma unroll
+        for (int j = 1; j < NV; ++j) a = mx ? fmax(a, v[j]) : a + v[j];
+        if (k < K)
+            for (int r = grp + NV * G; r < P.nb; r += G) a = mx ? fmax(a, rows[(size_t)r * K + k]) : a + rows[(size_t)r * K + k];
+        double o = __shfl_xor(a, 16, 64);
+        a = mx ? fmax(a, o) : a + o;
+        o = __shfl_xor(a, 32, 64);
+        a = mx ? fmax(a, o) : a + o;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        if (lane < 16) red[wave * 16 + lane] = a;
+        __syncthreads();
+        if (threadIdx.x < K) {
+            double t = red[threadIdx.x];
+            for (int w = 1; w < nw; ++w) t = mx ? fmax(t, red[w * 16 + threadIdx.x]) : t + red[w * 16 + threadIdx.x];
+            tot[threadIdx.x] = t;
         }
         __syncthreads();
-    };
-    merge(p0);
-    merge(p1);
-    merge(p2);
-    fin_step(*s, tot);
-    if (threadIdx.x == 0) s->b_phase = 0;
+    }
+};
+
+// What a pass that only reads the state fetches early.
+struct IntakeState {
+    StateChunk st;
+};
+// What a pass that absorbs a region of K-sum rows fetches early (NV rows per thread in registers).
+template <int K, int NV>
+struct IntakeAbsorb {
+    StateChunk st;
+    RowFetch<K, NV> rows;
+};
+
+// Copy the fetched state into LDS and barrier.
+__device__ __forceinline__ void state_copy(const Scal* in, int b, Scal* s, const StateChunk& ch) {
+    ch.store(in, b, s);
     __syncthreads();
 }
+
+// Thread 0 runs the scalar logic `fn(S, totals)` on the LDS state, with the totals copied into
+// registers first (so that stores to the state cannot force reloads of them), then barrier.  Only
+// the publishing block (blk 0) keeps the history pointer.
+template <int K, class F>
+__device__ __forceinline__ void finish(Scal* s, const double* tot, int blk, F fn) {
+    if (threadIdx.x == 0) {
+        double t[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) t[k] = tot[k];
+        if (blk != 0) s->hist = nullptr;
+        fn(*s, t);
+    }
+    __syncthreads();
+}
+
+// Start of an absorbing pass: the fetched state into LDS, the fetched rows reduced into `tot`
+// (LDS, K doubles; the reduction's barriers also publish the state), then `fn` on thread 0.
+template <int K, int NV, class F>
+__device__ __forceinline__ void absorb_finish(const Scal* in, int b, int blk, Scal* s, const IntakeAbsorb<K, NV>& it,
+                                              const Partials& P, unsigned mask, double* red, double* tot, F fn) {
+    it.st.store(in, b, s);
+    it.rows.reduce(P, b, mask, red, tot);
+    finish<K>(s, tot, blk, fn);
+}
+
+// Block 0 of the instance writes the LDS state to out[b] (after a barrier that made it final).
+__device__ __forceinline__ void state_publish(Scal* out, int b, int blk, const Scal* s) {
+    if (blk != 0) return;
+    const uint4* src = reinterpret_cast<const uint4*>(s);
+    uint4* dst = reinterpret_cast<uint4*>(out + b);
+    for (int c = threadIdx.x; c < kScalChunks; c += blockDim.x) dst[c] = src[c];
+}
+
+// The step at the start of phase A, from the direction sums of every pass of phase B (one region,
+// B sums), when they are pending: the line search and the predicted scalars of the new iterate.
+constexpr int kStepRowsPerThread = 16;   // 256 rows with 256-thread blocks
+using IntakeStep = IntakeAbsorb<B_K, kStepRowsPerThread>;
+__device__ __forceinline__ void intake_step(const Scal* in, const Partials& pb, int b, IntakeStep& it) {
+    it.st.issue(in, b);
+    it.rows.issue(pb, b, B_MAXMASK);
+}
+__device__ __forceinline__ void begin_step(const Scal* in, Scal* out, const Partials& pb, int b, int blk, double* red,
+                                           Scal* s, const IntakeStep& it) {
+    __shared__ double tot[B_K];
+    absorb_finish(in, b, blk, s, it, pb, B_MAXMASK, red, tot, [](Scal& S, const double* t) {
+        if (!S.done && S.b_phase) {
+            fin_step(S, t);
+            S.b_phase = 0;
+        }
+    });
+    state_publish(out, b, blk, s);
+}
+
+// Passes that absorb the phase-A sums (A_K per row, one region of at most 128 rows per thread
+// group's registers).
+constexpr int kARowsPerThread = 8;
+using IntakeA = IntakeAbsorb<A_K, kARowsPerThread>;
 
 // ---------------------------------------------------------------------------------------------
 // Phase A, first pass (x): [step from the direction sums], the pending retraction applied to
@@ -298,8 +410,10 @@ struct OpResid {
     IterFields<T> f;
     const Scal* Sin;  // S_dir
     Scal* Sout;       // S_step
-    Partials pb0, pb1, pb2;
+    Partials pb;      // the direction passes' rows (consumer view)
     int pre, post;
+    using Intake = IntakeStep;
+    __device__ void intake(int b, Intake& it) const { intake_step(Sin, pb, b, it); }
     struct State {
         C2<T> ph[8], lph[8], pp[8], lp[8];
         T V[8];
@@ -317,10 +431,8 @@ struct OpResid {
             st.V[q] = f.V[i];
         }
     }
-    __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s) const {
-        state_load(Sin, b, blk, s);
-        if (!s->done && s->b_phase) absorb_step(pb0, pb1, pb2, b, red, s);
-        state_publish(Sout, b, blk, s);
+    __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s, Intake& it) const {
+        begin_step(Sin, Sout, pb, b, blk, red, s, it);
     }
     __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K]) const {
         const Scal& s = *lc.sc;
@@ -387,6 +499,11 @@ struct OpPMid {
     const Scal* Sin;  // ABS: S_step; otherwise S_res
     Scal* Sout;       // ABS: S_res
     Partials pa1;
+    using Intake = std::conditional_t<ABS, IntakeA, IntakeState>;
+    __device__ void intake(int b, Intake& it) const {
+        it.st.issue(Sin, b);
+        if constexpr (ABS) it.rows.issue(pa1, b, A_MAXMASK);
+    }
     struct State {
         C2<T> w[8];
     };
@@ -394,15 +511,15 @@ struct OpPMid {
 #pragma unroll
         for (int q = 0; q < 8; ++q) st.w[q] = w[lc.at(q)];
     }
-    __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s) const {
-        state_load(Sin, b, blk, s);
+    __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s, Intake& it) const {
         if constexpr (ABS) {
-            if (!s->done) {
-                __shared__ double tot[A_K];
-                absorb<A_K>(pa1, b, A_MAXMASK, red, tot);
-                fin_residual(*s, tot);
-            }
+            __shared__ double tot[A_K];
+            absorb_finish(Sin, b, blk, s, it, pa1, A_MAXMASK, red, tot, [](Scal& S, const double* t) {
+                if (!S.done) fin_residual(S, t);
+            });
             state_publish(Sout, b, blk, s);
+        } else {
+            state_copy(Sin, b, s, it.st);
         }
     }
     __device__ void load(const Geo&, const LineCtx&, State& st, C2<T> (&v)[8], double (&)[1]) const {
@@ -441,30 +558,48 @@ struct OpPMid {
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 struct OpPLast {
-    static constexpr bool FWD = false, INV = true, SCALARS = true, PREFETCH = false;
+    static constexpr bool FWD = false, INV = true, SCALARS = true, PREFETCH = true;
     static constexpr int K = A_K;
     static constexpr unsigned MAXMASK = A_MAXMASK;
     IterFields<T> f;
     const Scal* Sin;  // S_res
     int post;
-    struct State {};
-    __device__ void begin(const Geo&, int b, int blk, double*, Scal* s) const { state_load(Sin, b, blk, s); }
-    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[K]) const {
+    // every input is fetched ahead: w for the transform, and what the epilogue and the CG sums read
+    struct State {
+        C2<T> w[8], ph[8], r[8], rp[8], pp[8];
+        T V[8];
+    };
+    __device__ void prefetch(const Geo&, const LineCtx& lc, State& st) const {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = f.w[lc.at(q)];
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = lc.at(q);
+            st.w[q] = f.w[i];
+            st.ph[q] = f.phi[i];
+            st.V[q] = f.V[i];
+            st.r[q] = f.r[i];
+            st.rp[q] = f.rp[i];
+            st.pp[q] = f.pp[i];
+        }
+    }
+    using Intake = IntakeState;
+    __device__ void intake(int b, Intake& it) const { it.st.issue(Sin, b); }
+    __device__ void begin(const Geo&, int b, int, double*, Scal* s, Intake& it) const { state_copy(Sin, b, s, it.st); }
+    __device__ void load(const Geo&, const LineCtx&, State& st, C2<T> (&v)[8], double (&)[K]) const {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = st.w[q];
     }
     __device__ void spectral(const Geo&, const LineCtx&, State&, C2<T> (&)[8], double (&)[K], C2<T>*,
                              const C2<T>*) const {}
-    __device__ void store(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[K]) const {
+    __device__ void store(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K]) const {
         const Scal& s = *lc.sc;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
-            const C2<T> ph = f.phi[i];
+            const C2<T> ph = st.ph[q];
             C2<T> pr = v[q];
-            if (post) pr = scl(pr, pscale<T>(post, pv_diag(s, (double)f.V[i], (double)abs2(ph))));
+            if (post) pr = scl(pr, pscale<T>(post, pv_diag(s, (double)st.V[q], (double)abs2(ph))));
             f.pr[i] = pr;
-            cg_sums<T>(acc, f.r[i], pr, f.rp[i], f.pp[i], ph);
+            cg_sums<T>(acc, st.r[q], pr, st.rp[q], st.pp[q], ph);
         }
     }
 };
@@ -478,47 +613,66 @@ struct OpPLast {
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX, bool FIRST, bool LAST>
 struct OpLp {
-    static constexpr bool FWD = true, INV = true, SCALARS = true, PREFETCH = FIRST;
+    static constexpr bool FWD = true, INV = true, SCALARS = true, PREFETCH = true;
+    static constexpr bool PHI = FIRST || LAST || AX < 2;  // phi is read (x, y: for the rotation sums when omega != 0)
     static constexpr int K = B_K;
     static constexpr unsigned MAXMASK = B_MAXMASK;
     IterFields<T> f;
     const Scal* Sin;   // FIRST: S_res (or S_step on the one-pass paths); otherwise S_dir
     Scal* Sout;        // FIRST: S_dir
-    Partials pres;     // FIRST: sums for the convergence test (one-pass paths), else empty
+    Partials pres;     // FIRST: set (to pdir's region) when the convergence test runs here (one-pass paths)
     Partials pdir;     // FIRST: sums for the CG direction
+    using Intake = std::conditional_t<FIRST, IntakeA, IntakeState>;
+    __device__ void intake(int b, Intake& it) const {
+        it.st.issue(Sin, b);
+        if constexpr (FIRST) it.rows.issue(pdir, b, A_MAXMASK);
+    }
     struct State {
         C2<T> ph[8];
         C2<T> p[8];
+        C2<T> w[FIRST ? 1 : 8];
+        T V[LAST ? 8 : 1];
     };
-    // FIRST: phi and the preconditioned residual P r (into p, where load() builds the new direction)
+    // phi (when read), P r (FIRST, from which load() builds the new direction) or p, and what the
+    // epilogue adds: the previous passes' partial L phat (w) and V
     __device__ void prefetch(const Geo&, const LineCtx& lc, State& st) const {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
-            st.ph[q] = f.phi[i];
-            st.p[q] = f.pr[i];
+            if constexpr (PHI) st.ph[q] = f.phi[i];
+            st.p[q] = FIRST ? f.pr[i] : f.pp[i];
+            if constexpr (!FIRST) st.w[q] = f.w[i];
+            if constexpr (LAST) st.V[q] = f.V[i];
         }
     }
-    __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s) const {
-        state_load(Sin, b, blk, s);
+    __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s, Intake& it) const {
         if constexpr (FIRST) {
+            // on the one-pass paths the convergence test reads the same region as the direction
             __shared__ double tot[A_K];
-            if (!s->done && pres.parts) {
-                absorb<A_K>(pres, b, A_MAXMASK, red, tot);
-                fin_residual(*s, tot);
-            }
-            if (!s->done) {
-                absorb<A_K>(pdir, b, A_MAXMASK, red, tot);
-                fin_direction(*s, tot);
-                if (threadIdx.x == 0 && !s->done) s->b_phase = 1;
+            it.st.store(Sin, b, s);
+            it.rows.reduce(pdir, b, A_MAXMASK, red, tot);
+            auto direction = [](Scal& S, const double* t) {
+                if (!S.done) {
+                    fin_direction(S, t);
+                    if (!S.done) S.b_phase = 1;
+                }
+            };
+            if (pres.parts) {
+                finish<A_K>(s, tot, blk, [direction](Scal& S, const double* t) {
+                    if (!S.done) fin_residual(S, t);
+                    direction(S, t);
+                });
+            } else {
+                finish<A_K>(s, tot, blk, direction);
             }
             state_publish(Sout, b, blk, s);
+        } else {
+            state_copy(Sin, b, s, it.st);
         }
     }
     __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&)[K]) const {
         const Scal& s = *lc.sc;
         const T inv = (T)(1.0 / s.pnorm);
-        const bool need_phi = LAST || (s.omega != 0.0 && AX < 2);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
@@ -528,8 +682,7 @@ struct OpLp {
                 p = sub(scl(f.pp[i], (T)s.beta_cg), add(st.p[q], scl(ph, (T)s.rho)));
                 f.pp[i] = p;
             } else {
-                p = f.pp[i];
-                if (need_phi) st.ph[q] = f.phi[i];
+                p = st.p[q];
             }
             st.p[q] = v[q] = scl(p, inv);
         }
@@ -564,12 +717,12 @@ struct OpLp {
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
             C2<T> o = v[q];
-            if constexpr (!FIRST) o = add(o, f.w[i]);
+            if constexpr (!FIRST) o = add(o, st.w[q]);
             if constexpr (!LAST) {
                 f.w[i] = o;
             } else {
                 const C2<T> ph = st.ph[q], p = st.p[q];
-                o = add(o, scl(p, f.V[i]));
+                o = add(o, scl(p, st.V[q]));
                 f.lp[i] = o;
                 // line-search sums (A = |phi|^2, B = Re conj(phi) phat, C = |phat|^2)
                 const double A = abs2(ph), Bq = redot(ph, p), Cq = abs2(p);
@@ -596,14 +749,14 @@ struct OpLp {
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, const Scal* Sin, Scal* Sout, int64_t N, int nbpi,
-                                                   int pre, Partials pb0, Partials pb1, Partials pb2, Partials pr) {
+                                                   int pre, Partials pb, Partials pr) {
     __shared__ double red[(256 / 64 + 1) * 16 + 8];
     __shared__ Scal s;
     const int b = blockIdx.x / nbpi;
     const int blk = blockIdx.x - b * nbpi;
-    state_load(Sin, b, blk, &s);
-    if (!s.done && s.b_phase) absorb_step(pb0, pb1, pb2, b, red, &s);
-    state_publish(Sout, b, blk, &s);
+    IntakeStep it;
+    intake_step(Sin, pb, b, it);
+    begin_step(Sin, Sout, pb, b, blk, red, &s, it);
     if (s.done) return;
     double acc[A_K];
 #pragma unroll
@@ -627,7 +780,7 @@ __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, const Scal*
     }
     __shared__ double totals[A_K];
     block_reduce<A_K>(acc, red, totals, A_MAXMASK);
-    double* P = pr.parts + ((size_t)b * nbpi + blk) * A_K;
+    double* P = pr.parts + ((size_t)b * pr.row_stride() + pr.off + blk) * A_K;
     for (int k = threadIdx.x; k < A_K; k += blockDim.x) P[k] = totals[k];
 }
 
@@ -636,11 +789,11 @@ __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, const Scal*
 // fixed order), so that the consuming pass's workgroups reduce a single row.
 // ---------------------------------------------------------------------------------------------
 template <int K>
-__global__ __launch_bounds__(256) void k_collapse(const double* parts, int nb, double* out, unsigned mask) {
-    __shared__ double red[(256 / 64) * K];
+__global__ __launch_bounds__(256) void k_collapse(const double* parts, int nb, int stride, double* out, unsigned mask) {
+    __shared__ double red[(256 / 64 + 1) * K];
     __shared__ double tot[K];
     const int b = blockIdx.x;
-    reduce_partials<K>(parts + (size_t)b * nb * K, nb, red, tot, mask);
+    reduce_partials<K>(parts + (size_t)b * stride * K, nb, red, tot, mask);
     for (int k = threadIdx.x; k < K; k += blockDim.x) out[(size_t)b * K + k] = tot[k];
 }
 
@@ -658,38 +811,38 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     Scal* S_dir = c.S + 2 * c.B;
     hipError_t e;
     auto region = [&](int r, int ax) {
-        Partials p;
-        p.parts = c.parts + (size_t)r * c.region_doubles;
-        p.counters = nullptr;
-        p.nb = pass_blocks_per_field(g, ax, cb, c.B);
-        return p;
+        const int nb = pass_blocks_per_field(g, ax, cb, c.B);
+        return Partials{c.parts + (size_t)r * c.region_doubles, nb, nb, 0};
     };
     // the view a consumer absorbs: the region itself, or its one-row collapse for many rows
     auto consumable = [&](const Partials& p, int rc, int K, unsigned mask) -> Partials {
         if (p.nb <= kAbsorbRows) return p;
-        Partials q{c.parts + (size_t)rc * c.region_doubles, nullptr, 1};
+        const Partials q{c.parts + (size_t)rc * c.region_doubles, 1, 1, 0};
         if (K == A_K)
-            hipLaunchKernelGGL(k_collapse<A_K>, dim3((unsigned)c.B), dim3(256), 0, s, p.parts, p.nb, q.parts, mask);
+            hipLaunchKernelGGL(k_collapse<A_K>, dim3((unsigned)c.B), dim3(256), 0, s, p.parts, p.nb, p.row_stride(),
+                               q.parts, mask);
         else
-            hipLaunchKernelGGL(k_collapse<B_K>, dim3((unsigned)c.B), dim3(256), 0, s, p.parts, p.nb, q.parts, mask);
+            hipLaunchKernelGGL(k_collapse<B_K>, dim3((unsigned)c.B), dim3(256), 0, s, p.parts, p.nb, p.row_stride(),
+                               q.parts, mask);
         return q;
     };
-    const Partials none{nullptr, nullptr, 0};
+    const Partials none{nullptr, 0, 0, 0};
     // algorithmic bytes of a launch: `reals` real numbers of sizeof(T) per grid point and instance
     const double unit = (double)sizeof(T) * (double)g.N * (double)c.B;
     auto tick = [&](const char* name, double reals) {
         if (c.timer) c.timer->mark(s, name, reals * unit);
     };
-    // partial regions of the direction passes (absorbed by the step at the next iteration's start,
-    // through their collapsed rows when they have many)
-    const Partials pb0 = region(R_B0, 0);
-    const Partials pb1 = g.dim >= 2 ? region(R_B1, 1) : none;
-    const Partials pb2 = g.dim >= 3 ? region(R_B2, 2) : none;
-    auto view = [&](const Partials& p, int rc) -> Partials {
-        if (!p.parts || p.nb <= kAbsorbRows) return p;
-        return Partials{c.parts + (size_t)rc * c.region_doubles, nullptr, 1};
-    };
-    const Partials sb0 = view(pb0, R_B0C), sb1 = view(pb1, R_B1C), sb2 = view(pb2, R_B2C);
+    // The direction passes (x, y, z) share one region of B-sum rows, each pass at its own offset
+    // within an instance's rows; the step absorbs them at the next iteration's start, through their
+    // one-row collapse when they are many.
+    const int nbx = pass_blocks_per_field(g, 0, cb, c.B);
+    const int nby = g.dim >= 2 ? pass_blocks_per_field(g, 1, cb, c.B) : 0;
+    const int nbz = g.dim >= 3 ? pass_blocks_per_field(g, 2, cb, c.B) : 0;
+    const int nbB = nbx + nby + nbz;
+    double* const partsB = c.parts + (size_t)R_B * c.region_doubles;
+    const Partials pb0{partsB, nbx, nbB, 0}, pb1{partsB, nby, nbB, nbx}, pb2{partsB, nbz, nbB, nbx + nby};
+    const Partials pbAll{partsB, nbB, nbB, 0};
+    const Partials sb = nbB <= kAbsorbRows ? pbAll : Partials{c.parts + (size_t)R_BC * c.region_doubles, 1, 1, 0};
     // ---- phase A ----
     int pre = 0, post = 0;
     const bool spectral_p = c.precond == GPE_P_KINETIC || c.precond == GPE_P_COMBINED || c.precond == GPE_P_C1 ||
@@ -702,16 +855,16 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     if (!spectral_p) {
         // diagonal P (identity or P_V): one pointwise kernel for residual, P r and every sum
         const int nbpi = c.pointwise_blocks;
-        Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, nullptr, nbpi};
+        const Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, nbpi, nbpi, 0};
         tick("step_resid_diag", 21);
         hipLaunchKernelGGL(k_resid_diag<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f, S_dir, S_step, g.N, nbpi,
-                           pre, sb0, sb1, sb2, pr);
+                           pre, sb, pr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         pres = consumable(pr, R_A1C, A_K, A_MAXMASK);
         pdir = pres;
         dir_in = S_step;
     } else if (g.dim == 1) {
-        OpResid<T, true> op{f, S_dir, S_step, sb0, sb1, sb2, pre, post};
+        OpResid<T, true> op{f, S_dir, S_step, sb, pre, post};
         tick("step_resid_precond_x", 21);
         const Partials pa = region(R_A1, 0);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa, s)) != hipSuccess) return e;
@@ -719,7 +872,7 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         pdir = pres;
         dir_in = S_step;
     } else {
-        OpResid<T, false> op{f, S_dir, S_step, sb0, sb1, sb2, pre, post};
+        OpResid<T, false> op{f, S_dir, S_step, sb, pre, post};
         tick("step_resid_fwd_x", 17);
         const Partials pa1r = region(R_A1, 0);
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa1r, s)) != hipSuccess) return e;
@@ -769,9 +922,7 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         tick("Lp_z_linesearch", 9);
         if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), oz, pb2, s)) != hipSuccess) return e;
     }
-    (void)consumable(pb0, R_B0C, B_K, B_MAXMASK);
-    if (pb1.parts) (void)consumable(pb1, R_B1C, B_K, B_MAXMASK);
-    if (pb2.parts) (void)consumable(pb2, R_B2C, B_K, B_MAXMASK);
+    (void)consumable(pbAll, R_BC, B_K, B_MAXMASK);
     return hipGetLastError();
 }
 

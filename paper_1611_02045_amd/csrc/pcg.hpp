@@ -20,11 +20,10 @@ struct IterFields {
     T* V;         // potential
 };
 
-// Partial-sum regions (one per reducing kernel) and their ticket counters.
 // Partial-sum regions of the reducing passes, and their collapsed counterparts (one row per
 // instance) used when a pass has more workgroups per instance than a consumer should re-reduce.
 enum : int {
-    R_A1 = 0, R_A3, R_B0, R_B1, R_B2, R_A1C, R_A3C, R_B0C, R_B1C, R_B2C, R_COUNT
+    R_A1 = 0, R_A3, R_B, R_A1C = R_B + 3, R_A3C, R_BC, R_COUNT  // R_B spans three regions (x, y, z passes)
 };
 constexpr int kAbsorbRows = 256;
 
@@ -118,7 +117,7 @@ __device__ __forceinline__ void apply_step_pref(const IterFields<T>& f, const Sc
     if (s.has_step) {
         const C2<T> np = add(scl(ph, (T)s.c_phi), scl(pp, (T)s.c_p));
         const C2<T> nl = add(scl(lph, (T)s.c_L), scl(lpv, (T)s.c_Lp));
-        acc[A_DPHI] = fmax(acc[A_DPHI], sqrt((double)abs2(sub(np, ph))));
+        acc[A_DPHI] = fmax(acc[A_DPHI], (double)abs2(sub(np, ph)));  // squared; the root is taken once
         f.phi[i] = np;
         f.Lphi[i] = nl;
         ph = np;
@@ -139,9 +138,9 @@ __device__ __forceinline__ void apply_step(const IterFields<T>& f, const Scal& s
 
 template <typename T>
 __device__ __forceinline__ void res_sums(double* acc, C2<T> r) {
-    const double m = sqrt((double)abs2(r));
-    acc[A_RES] = fmax(acc[A_RES], m);
-    if (!isfinite(m)) acc[A_NF] = 1.0;
+    const double m2 = (double)abs2(r);  // max of |r|^2; the root of the maximum is taken once
+    acc[A_RES] = fmax(acc[A_RES], m2);
+    if (!isfinite(m2)) acc[A_NF] = 1.0;
 }
 
 template <typename T>
