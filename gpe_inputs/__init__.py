@@ -28,6 +28,8 @@ SEED_3D = 104
 SEED_PINS = 105
 SEED_THETA_TARGET = 106
 SEED_BATCH_BASE = 2000
+# seeded vortex-seed starts of the 2-D 512^2 time-to-tolerance workload (the first is SEED_2D_512)
+SEEDS_2D_512_SET = (103, 107, 109, 113)
 
 
 @dataclass(frozen=True)
@@ -207,6 +209,12 @@ def workload_2d(M: int = 512, seed: int | None = None, beta: float = 1000.0, ome
     if seed is None:
         seed = SEED_2D_512 if M == 512 else SEED_2D_256
     return prob, harmonic_potential(prob), vortex_seed_2d(prob, seed)
+
+
+def workload_2d_set(M: int = 512, seeds=SEEDS_2D_512_SET):
+    """The 2-D fast-rotation problem with several seeded vortex-seed starts (same V, beta, Omega)."""
+    prob, V, _ = workload_2d(M, seeds[0])
+    return prob, V, [vortex_seed_2d(prob, s) for s in seeds]
 
 
 def workload_3d(M: int = 128):

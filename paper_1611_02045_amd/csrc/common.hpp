@@ -81,14 +81,14 @@ struct alignas(16) Scal {
     double theta, c_phi, c_p, c_L, c_Lp, dE;
     // counters and flags
     int64_t n, restarts, halvings, iters_fp32;
-    int32_t done, status, have_prev, linesearch_fail;
+    int32_t done, status, have_prev, linesearch_fail;  // linesearch_fail: consecutive failures
     int32_t stagnant, nonfinite, b_phase, precision;   // b_phase: direction partials are pending
     // options copied per instance
     double tol_res, tol_energy, theta_default;
     int32_t method, beta_rule, max_halvings, precond;
     int64_t max_iter;
     // stagnation tracking (mixed precision)
-    double best_res;
+    double best_res, best_E;
     int64_t best_n;
     double switch_res;
     int32_t stall_window, has_step;   // has_step: a retraction step is pending (applied by phase A)

@@ -3,9 +3,26 @@
 
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "passes.hpp"
 
 namespace gpe {
+
+// Optional start/stop events a launch records around its own execution (per-kernel timing).
+struct LaunchEvents {
+    hipEvent_t start, stop;
+};
+
+// hipLaunchKernelGGL, or its event-recording form when timing.
+template <typename K, typename... Args>
+inline void launch_timed(const LaunchEvents* ev, K kern, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                         Args... args) {
+    if (ev)
+        hipExtLaunchKernelGGL(kern, grid, block, lds, s, ev->start, ev->stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+}
 
 constexpr size_t kPassLdsBudget = 96 * 1024;
 // Workgroup size cap of the passes: with 256 threads (one wave per SIMD) every kernel may keep up
@@ -51,7 +68,8 @@ inline int pass_blocks_per_field(const Geo& g, int AX, int complex_bytes, int B 
 
 // Launch one pass over B instances.  `pr` receives nb (blocks per instance) if the Op reduces.
 template <typename T, int AX, class Op>
-hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partials pr, hipStream_t s) {
+hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partials pr, hipStream_t s,
+                       const LaunchEvents* ev = nullptr) {
     const int cb = (int)sizeof(C2<T>);
     const int C = pass_lines_per_block(g, AX, cb, B);
     const int TPL = g.n[AX] / 8;
@@ -71,8 +89,7 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
             (void)hipGetLastError();
         attr_set = true;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)(nb * (int64_t)B)), dim3(threads), lds, s, g, C,
-                       (const C2<T>*)tw, op, pr);
+    launch_timed(ev, kern, dim3((unsigned)(nb * (int64_t)B)), dim3(threads), lds, s, g, C, (const C2<T>*)tw, op, pr);
     return hipGetLastError();
 }
 

@@ -97,9 +97,15 @@ __device__ __forceinline__ void fin_residual(Scal& S, const double* t) {
             S.status = ST_NOT_CONVERGED;
             S.done = 1;
         } else if (S.stall_window > 0) {
-            // mixed precision: leave the FP32 phase when the residual stops improving
-            if (res < S.best_res * (1.0 - 1e-3)) {
-                S.best_res = res;
+            // mixed precision: leave the FP32 phase once neither the residual (by 10%) nor the
+            // energy (by 1e-9 relative) has improved for stall_window iterations.  The residual
+            // alone plateaus for hundreds of iterations while vortices still move; the energy
+            // keeps falling then, and stops only at the FP32 floor.
+            const bool better_res = res < 0.9 * S.best_res;
+            const bool better_E = S.E < S.best_E - 1e-9 * fabs(S.E);
+            if (better_res) S.best_res = res;
+            if (better_E) S.best_E = S.E;
+            if (better_res || better_E) {
                 S.best_n = S.n;
             } else if (S.n - S.best_n >= S.stall_window) {
                 S.stagnant = 1;
@@ -197,16 +203,25 @@ __device__ __forceinline__ void fin_step(Scal& S, const double* t) {
             S.nonfinite = 1;
             S.done = 1;
         } else if (acc_t < 0.0) {
-            // no trial decreased the energy: in FP32 this ends the phase (switch to FP64)
-            S.linesearch_fail = 1;
-            if (S.precision == 1) {
-                S.stagnant = 1;
-                S.status = ST_OK;
+            // No trial decreased the energy.  In FP64 this is an error.  In FP32 the first failure
+            // is retried from a steepest-descent direction (no step, CG memory dropped); a second
+            // one in a row ends the phase (switch to FP64).
+            S.linesearch_fail += 1;
+            if (S.precision == 1 && S.linesearch_fail < 2) {
+                S.have_prev = 0;
+                S.n += 1;
+                S.iters_fp32 += 1;
             } else {
-                S.status = ST_LINESEARCH;
+                if (S.precision == 1) {
+                    S.stagnant = 1;
+                    S.status = ST_OK;
+                } else {
+                    S.status = ST_LINESEARCH;
+                }
+                S.done = 1;
             }
-            S.done = 1;
         } else {
+            S.linesearch_fail = 0;
             const double n2 = c * c * S.nrm2 + 2.0 * c * s * SB + s * s * SC;
             const double nu = 1.0 / sqrt(n2);
             S.theta = acc_t;
@@ -829,8 +844,8 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     const Partials none{nullptr, 0, 0, 0};
     // algorithmic bytes of a launch: `reals` real numbers of sizeof(T) per grid point and instance
     const double unit = (double)sizeof(T) * (double)g.N * (double)c.B;
-    auto tick = [&](const char* name, double reals) {
-        if (c.timer) c.timer->mark(s, name, reals * unit);
+    auto tick = [&](const char* name, double reals) -> const LaunchEvents* {
+        return c.timer ? c.timer->next(name, reals * unit) : nullptr;
     };
     // The direction passes (x, y, z) share one region of B-sum rows, each pass at its own offset
     // within an instance's rows; the step absorbs them at the next iteration's start, through their
@@ -856,71 +871,81 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         // diagonal P (identity or P_V): one pointwise kernel for residual, P r and every sum
         const int nbpi = c.pointwise_blocks;
         const Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, nbpi, nbpi, 0};
-        tick("step_resid_diag", 21);
-        hipLaunchKernelGGL(k_resid_diag<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f, S_dir, S_step, g.N, nbpi,
-                           pre, sb, pr);
+        launch_timed(tick("step_resid_diag", 21), k_resid_diag<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f,
+                     S_dir, S_step, g.N, nbpi, pre, sb, pr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         pres = consumable(pr, R_A1C, A_K, A_MAXMASK);
         pdir = pres;
         dir_in = S_step;
     } else if (g.dim == 1) {
         OpResid<T, true> op{f, S_dir, S_step, sb, pre, post};
-        tick("step_resid_precond_x", 21);
         const Partials pa = region(R_A1, 0);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa, s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa, s,
+                tick("step_resid_precond_x", 21))) != hipSuccess)
+            return e;
         pres = consumable(pa, R_A1C, A_K, A_MAXMASK);
         pdir = pres;
         dir_in = S_step;
     } else {
         OpResid<T, false> op{f, S_dir, S_step, sb, pre, post};
-        tick("step_resid_fwd_x", 17);
         const Partials pa1r = region(R_A1, 0);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa1r, s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pa1r, s,
+                tick("step_resid_fwd_x", 17))) != hipSuccess)
+            return e;
         const Partials pa1 = consumable(pa1r, R_A1C, A_K, A_MAXMASK);
         if (g.dim == 2) {
             OpPMid<T, 1, true, true, true> y{f.w, S_step, S_res, pa1};
-            tick("resid_test_precond_y", 4);
-            if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y, none, s)) != hipSuccess) return e;
+            if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y, none, s,
+                    tick("resid_test_precond_y", 4))) != hipSuccess)
+                return e;
         } else {
             OpPMid<T, 1, true, false, true> y1{f.w, S_step, S_res, pa1};
-            tick("resid_test_precond_fwd_y", 4);
-            if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y1, none, s)) != hipSuccess) return e;
+            if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y1, none, s,
+                    tick("resid_test_precond_fwd_y", 4))) != hipSuccess)
+                return e;
             OpPMid<T, 2, true, true, false> z{f.w, S_res, nullptr, none};
-            tick("precond_z", 4);
-            if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), z, none, s)) != hipSuccess) return e;
+            if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), z, none, s,
+                    tick("precond_z", 4))) != hipSuccess)
+                return e;
             OpPMid<T, 1, false, true, false> y2{f.w, S_res, nullptr, none};
-            tick("precond_inv_y", 4);
-            if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y2, none, s)) != hipSuccess) return e;
+            if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), y2, none, s,
+                    tick("precond_inv_y", 4))) != hipSuccess)
+                return e;
         }
         OpPLast<T> op3{f, S_res, post};
-        tick("precond_inv_x", 13);
         const Partials pa3 = region(R_A3, 0);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op3, pa3, s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op3, pa3, s,
+                tick("precond_inv_x", 13))) != hipSuccess)
+            return e;
         pdir = consumable(pa3, R_A3C, A_K, A_MAXMASK);
         dir_in = S_res;
     }
     // ---- phase B ----
     if (g.dim == 1) {
         OpLp<T, 0, true, true> op{f, dir_in, S_dir, pres, pdir};
-        tick("dir_Lp_x_linesearch", 11);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pb0, s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), op, pb0, s,
+                tick("dir_Lp_x_linesearch", 11))) != hipSuccess)
+            return e;
     } else if (g.dim == 2) {
         OpLp<T, 0, true, false> ox{f, dir_in, S_dir, pres, pdir};
-        tick("dir_Lp_x", 10);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, pb0, s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, pb0, s,
+                tick("dir_Lp_x", 10))) != hipSuccess)
+            return e;
         OpLp<T, 1, false, true> oy{f, S_dir, nullptr, none, none};
-        tick("Lp_y_linesearch", 9);
-        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, pb1, s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, pb1, s,
+                tick("Lp_y_linesearch", 9))) != hipSuccess)
+            return e;
     } else {
         OpLp<T, 0, true, false> ox{f, dir_in, S_dir, pres, pdir};
-        tick("dir_Lp_x", 10);
-        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, pb0, s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, pb0, s,
+                tick("dir_Lp_x", 10))) != hipSuccess)
+            return e;
         OpLp<T, 1, false, false> oy{f, S_dir, nullptr, none, none};
-        tick("Lp_y", 8);
-        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, pb1, s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, pb1, s, tick("Lp_y", 8))) != hipSuccess) return e;
         OpLp<T, 2, false, true> oz{f, S_dir, nullptr, none, none};
-        tick("Lp_z_linesearch", 9);
-        if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), oz, pb2, s)) != hipSuccess) return e;
+        if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), oz, pb2, s,
+                tick("Lp_z_linesearch", 9))) != hipSuccess)
+            return e;
     }
     (void)consumable(pbAll, R_BC, B_K, B_MAXMASK);
     return hipGetLastError();

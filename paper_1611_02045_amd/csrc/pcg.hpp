@@ -2,7 +2,7 @@
 #pragma once
 
 #include "internal.hpp"
-#include "passes.hpp"
+#include "launch.hpp"
 
 namespace gpe {
 
@@ -27,44 +27,49 @@ enum : int {
 };
 constexpr int kAbsorbRows = 256;
 
-// Optional per-kernel timing of an iteration with HIP events recorded on the iteration's stream
-// between consecutive launches (used by gpe_pcg_profile).
+// Optional per-kernel timing of an iteration (gpe_pcg_profile): every launch of the iteration
+// records a start/stop event pair with the launch itself, which brackets that kernel's execution
+// alone (the dispatch gaps between kernels are not counted).
 struct KernelTimer {
     static constexpr int MAX = 16;
     int n = 0;
-    hipEvent_t ev[MAX + 1] = {};
+    hipEvent_t ev0[MAX] = {}, ev1[MAX] = {};
     const char* names[MAX] = {};
     double bytes[MAX] = {};
     double total_ms[MAX] = {};
     int64_t launches[MAX] = {};
     int slots = 0;
     hipError_t init() {
-        for (int k = 0; k <= MAX; ++k) {
-            hipError_t e = hipEventCreate(&ev[k]);
+        for (int k = 0; k < MAX; ++k) {
+            hipError_t e = hipEventCreate(&ev0[k]);
+            if (e == hipSuccess) e = hipEventCreate(&ev1[k]);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
     void destroy() {
-        for (int k = 0; k <= MAX; ++k)
-            if (ev[k]) (void)hipEventDestroy(ev[k]);
+        for (int k = 0; k < MAX; ++k) {
+            if (ev0[k]) (void)hipEventDestroy(ev0[k]);
+            if (ev1[k]) (void)hipEventDestroy(ev1[k]);
+        }
     }
-    // before a launch: close the previous slot and open slot n
-    void mark(hipStream_t s, const char* name, double b) {
-        if (n >= MAX) return;
-        (void)hipEventRecord(ev[n], s);
+    // the start/stop event pair the next launch records (its own execution interval), or null
+    const LaunchEvents* next(const char* name, double b) {
+        if (n >= MAX) return nullptr;
         names[n] = name;
         bytes[n] = b;
+        pair = LaunchEvents{ev0[n], ev1[n]};
         ++n;
+        return &pair;
     }
-    // after an iteration: record the end, wait, and accumulate the slot durations
-    hipError_t collect(hipStream_t s) {
-        (void)hipEventRecord(ev[n], s);
-        hipError_t e = hipEventSynchronize(ev[n]);
+    // after an iteration: wait, and accumulate the launch durations
+    hipError_t collect() {
+        if (n == 0) return hipSuccess;
+        hipError_t e = hipEventSynchronize(ev1[n - 1]);
         if (e != hipSuccess) return e;
         for (int k = 0; k < n; ++k) {
             float ms = 0.0f;
-            e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            e = hipEventElapsedTime(&ms, ev0[k], ev1[k]);
             if (e != hipSuccess) return e;
             total_ms[k] += ms;
             launches[k] += 1;
@@ -73,6 +78,7 @@ struct KernelTimer {
         n = 0;
         return hipSuccess;
     }
+    LaunchEvents pair{};
 };
 
 template <typename T>

@@ -89,6 +89,7 @@ __global__ void k_scal_from_parts(Scal* S, const double* parts, int restart_cg) 
         s.has_step = 0;
         s.E_prev = E;
         s.best_res = 1e300;
+        s.best_E = 1e300;
         s.best_n = s.n;
     }
     s.E = E;
@@ -319,7 +320,7 @@ hipError_t profile_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host
     c.timer = &timer;
     for (int k = 0; k < iters; ++k) {
         if ((e = enqueue_iteration<T>(c, s)) != hipSuccess) return e;
-        if ((e = timer.collect(s)) != hipSuccess) return e;
+        if ((e = timer.collect()) != hipSuccess) return e;
         std::swap(c.f.r, c.f.rp);
     }
     return hipMemcpy(host_S.data(), S_dir, sizeof(Scal) * pa.B, hipMemcpyDeviceToHost);
@@ -402,6 +403,7 @@ Scal make_scal(const gpe_problem_t& p, const Geo& g, const gpe_pcg_opts_t& o) {
     s.max_iter = o.max_iter;
     s.switch_res = o.switch_res;
     s.best_res = 1e300;
+    s.best_E = 1e300;
     return s;
 }
 
