@@ -92,6 +92,38 @@ def mean(xs):
     return float(sum(xs)) / len(xs)
 
 
+def kernel_rows(prof):
+    return [{"name": n, "avg_ms": m, "bytes": b, "GB_s": b / (m * 1e-3) / 1e9} for n, m, b in prof]
+
+
+def source_digest():
+    """Digest of the HIP sources: counter figures taken from an older build no longer apply."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1611_02045_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken from
+    these exact sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_2d_512.md")
+    try:
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("traffic-json:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec.get("source_digest") == source_digest() and kernel in rec.get("kernels", {}):
+                        return rec["kernels"][kernel]["hbm_bytes_per_launch"]
+    except OSError:
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +132,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=30)
+    ap.add_argument("--batched", action="store_true",
+                    help="also solve the four starts as one batched solve (mixed and FP64)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the per-kernel profile of the iteration and a 512 MiB copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver is a single-GPU "
@@ -129,6 +165,18 @@ def main():
     def step_inputs():
         return [x.clone() for x in starts0]
 
+    if args.profile_only:
+        prof32 = plan.profile(V, phi0, iters=args.profile_iters, precision="mixed")
+        prof64 = plan.profile(V, phi0, iters=args.profile_iters, precision="fp64")
+        # a plain copy of known size, to scale the HBM byte counters
+        a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_only": True, "copy_bytes": a.numel(),
+                          "kernels": {"fp32": kernel_rows(prof32), "fp64": kernel_rows(prof64)}}), flush=True)
+        return
+
     log(f"[bench] warmup {args.warmup} step(s) of {len(starts0)} mixed solves + 1 fp64 solve")
     for _ in range(args.warmup):
         time_solves(torch, plan, V, step_inputs(), **mixed)
@@ -149,8 +197,8 @@ def main():
     log(f"[bench] fp64:  {t_fp64:.4f} s/solve, iters {[r['iters'] for r in reps_fp64]}")
 
     # the same starts as one batched solve (per-instance convergence masks)
-    batched = {}
-    for tag, opts in (("mixed", mixed), ("fp64", fp64)):
+    batched = None if not args.batched else {}
+    for tag, opts in ((("mixed", mixed), ("fp64", fp64)) if args.batched else ()):
         phis = step_inputs()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -186,9 +234,11 @@ def main():
     totals.sort(reverse=True)
     _, tag, name, ms, by = totals[0]
     achieved = by / (ms * 1e-3) / 1e9
+    kname = f"{name} ({tag})"
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": f"{name} ({tag})", "bytes_per_launch": by, "avg_ms": ms}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
+                "kernel": kname, "bytes_per_launch": by, "avg_ms": ms,
+                "timing": "HIP start/stop events recorded by each launch (kernel execution only)"}
 
     it_fp64 = [r["iters"] for r in reps_fp64]
     cpu = None
@@ -229,8 +279,7 @@ def main():
                   "res_mixed": max(r["res_inf"] for r in reps_mixed),
                   "E_fp64": [r["E"] for r in reps_fp64[:len(starts0)]],
                   "res_fp64": max(r["res_inf"] for r in reps_fp64)},
-        "kernels": {"fp32": [{"name": n, "avg_ms": m, "bytes": b, "GB_s": b / (m * 1e-3) / 1e9} for n, m, b in prof32],
-                    "fp64": [{"name": n, "avg_ms": m, "bytes": b, "GB_s": b / (m * 1e-3) / 1e9} for n, m, b in prof64]},
+        "kernels": {"fp32": kernel_rows(prof32), "fp64": kernel_rows(prof64)},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

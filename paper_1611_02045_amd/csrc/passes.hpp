@@ -58,7 +58,13 @@ __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
         lc.t = tid >> lgC;
     }
     const int lg_lpf = g.lg[0] + g.lg[1] + g.lg[2] - lc.lg;  // log2 of the lines per field
-    const int64_t line = ((int64_t)blockIdx.x << lgC) + lc.c;
+    // Workgroups are dealt to the 8 XCDs round robin (workgroup i to XCD i mod 8), each with its
+    // own L2.  A strided pass's workgroup reads C adjacent columns, a fraction of each 128-byte
+    // line, so neighbouring column groups are given to workgroups on the same XCD: logical group
+    // x * G/8 + j runs as workgroup 8 j + x, and the XCD's L2 serves each line to all of them.
+    unsigned grp = blockIdx.x;
+    if (AX != 0 && (gridDim.x & 7u) == 0) grp = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const int64_t line = ((int64_t)grp << lgC) + lc.c;
     lc.b = (int)(line >> lg_lpf);
     const int64_t lf = line & (((int64_t)1 << lg_lpf) - 1);
     blk = (int)(lf >> lgC);
