@@ -29,7 +29,7 @@ SEED_PINS = 105
 SEED_THETA_TARGET = 106
 SEED_BATCH_BASE = 2000
 # seeded vortex-seed starts of the 2-D 512^2 time-to-tolerance workload (the first is SEED_2D_512)
-SEEDS_2D_512_SET = (103, 107, 109, 113)
+SEEDS_2D_512_SET = (103, 107, 109, 113, 127, 131, 137, 139)
 
 
 @dataclass(frozen=True)

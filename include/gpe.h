@@ -177,15 +177,24 @@ int gpe_adjoint_solve(gpe_plan_t* plan, const void* phi_star, const void* V, con
 int gpe_adjoint_param_grads(gpe_plan_t* plan, const void* phi_star, const void* mu, void* grad_V,
                             double* dl_dbeta, double* dl_domega, void* stream);
 
-/* Instrumented run for measurement: `iters` solver iterations at the precision of
- * opts->precision (0: FP64 fields, 1: FP32 fields; an FP32 plan always uses FP32) from phi
- * (device, left unchanged), with every kernel launch of an iteration bracketed by HIP events
- * on `stream`.  Host outputs, `cap` entries each: avg_ms[k] = mean event-to-event time of the
- * k-th kernel of the iteration, bytes[k] = its algorithmic HBM bytes per launch (fields read
- * and written once), names = cap rows of 32 chars.  Returns the number of kernels per
- * iteration (>= 0) or an error.  The convergence test is disabled during the run. */
+/* Instrumented run for measurement (the iteration of Section 5.2, Algorithm 2): `iters` solver
+ * iterations at the precision of opts->precision (0: FP64 fields, 1: FP32 fields; an FP32 plan
+ * always uses FP32) from phi (device, left unchanged), every kernel launch of an iteration
+ * recording a start/stop HIP event pair on `stream` around its own execution.  Host outputs,
+ * `cap` entries each: avg_ms[k] = mean execution time of the k-th kernel of the iteration,
+ * bytes[k] = its algorithmic HBM bytes per launch (fields read and written once), names = cap
+ * rows of 32 chars.  Returns the number of kernels per iteration (>= 0) or an error.  The
+ * convergence test is disabled during the run. */
 int gpe_pcg_profile(gpe_plan_t* plan, const void* V, const void* phi, const gpe_pcg_opts_t* opts, int iters,
                     int cap, double* avg_ms, double* bytes, char* names, void* stream);
+
+/* As gpe_pcg_profile for `count` instances of one grid solved together as in
+ * gpe_pcg_solve_batched (same argument conventions: probs[i], V[i], phi[i] device fields of type
+ * `dtype`, left unchanged); bytes[k] counts all instances.  Allocates and frees its own
+ * workspace.  GPE_EINVAL if the instances do not share (dim, n). */
+int gpe_pcg_profile_batched(int count, const gpe_problem_t* probs, int dtype, const void* const* V,
+                            const void* const* phi, const gpe_pcg_opts_t* opts, int iters, int cap, double* avg_ms,
+                            double* bytes, char* names, void* stream);
 
 /* Message of the last error on this thread ("" if none). */
 const char* gpe_last_error(void);

@@ -52,6 +52,89 @@ int run(BatchWork& w, int B, IterFields<T> f, std::vector<Scal>& hs, const gpe_p
     return GPE_OK;
 }
 
+// Workspace of an instrumented run.
+struct ProfileWork {
+    Geo g;
+    const Twiddles* tw;
+    Reduce* red;
+    DevBuf* scal;
+    DevBuf* f64;   // FP64 fields
+    DevBuf* f32;   // FP32 fields
+};
+
+// `iters` instrumented iterations of B instances of one grid at the precision of o (FP32 fields
+// for an FP32 input or a mixed solve), from copies of phi[b]; the kernel durations of an iteration
+// are averaged over the iterations.  Returns the number of kernels per iteration or an error.
+int profile_group(ProfileWork& w, int B, const gpe_problem_t* probs, bool in_f64, const void* const* V,
+                  const void* const* phi, const gpe_pcg_opts_t& opts, int iters, int cap, double* avg_ms,
+                  double* bytes, char* names, hipStream_t s) {
+    const Geo& g = w.g;
+    const int64_t N = g.N;
+    HIPCHK(reduce_init(*w.red, B, R_COUNT, std::max<size_t>(1 << 18, R_COUNT * region_doubles_for(g, B))));
+    HIPCHK(w.scal->ensure(3 * sizeof(Scal) * (size_t)B));
+    gpe_pcg_opts_t o = opts;
+    o.tol_res_inf = 0.0;
+    o.tol_energy = 0.0;
+    o.max_iter = (int64_t)iters + 1000;
+    std::vector<Scal> hs(B);
+    for (int b = 0; b < B; ++b) hs[b] = make_scal(probs[b], make_geo(probs[b]), o);
+    PhaseArgs pa;
+    pa.g = g;
+    pa.B = B;
+    pa.tw = w.tw;
+    pa.S = (Scal*)w.scal->ptr;
+    pa.red = w.red;
+    pa.region_doubles = region_doubles_for(g, B);
+    pa.precond = o.precond;
+    pa.check_every = 1;
+    pa.refresh_every = 0;
+    pa.final_f_r_is_rp = false;
+    KernelTimer timer;
+    hipError_t e = timer.init();
+    const bool fp32 = !in_f64 || o.precision == 1;
+    const size_t cb = in_f64 ? 16 : 8, rb = in_f64 ? 8 : 4;
+    if (e == hipSuccess) {
+        if (fp32) {
+            IterFields<float> f = carve_fields<float>(*w.f32, (int64_t)B * N, &e);
+            for (int b = 0; b < B && e == hipSuccess; ++b) {
+                if (in_f64) {
+                    e = convert_complex(false, phi[b], f.phi + (int64_t)b * N, N, s);
+                    if (e == hipSuccess) e = convert_real(false, V[b], f.V + (int64_t)b * N, N, s);
+                } else {
+                    e = copy_bytes(phi[b], f.phi + (int64_t)b * N, cb * N, s);
+                    if (e == hipSuccess) e = copy_bytes(V[b], f.V + (int64_t)b * N, rb * N, s);
+                }
+            }
+            if (e == hipSuccess) e = profile_phase<float>(pa, f, hs, iters, timer, s);
+        } else {
+            IterFields<double> f = carve_fields<double>(*w.f64, (int64_t)B * N, &e);
+            for (int b = 0; b < B && e == hipSuccess; ++b) {
+                e = copy_bytes(phi[b], f.phi + (int64_t)b * N, cb * N, s);
+                if (e == hipSuccess) e = copy_bytes(V[b], f.V + (int64_t)b * N, rb * N, s);
+            }
+            if (e == hipSuccess) e = profile_phase<double>(pa, f, hs, iters, timer, s);
+        }
+    }
+    int n = 0;
+    if (e == hipSuccess) {
+        n = std::min(timer.slots, cap);
+        for (int k = 0; k < n; ++k) {
+            avg_ms[k] = timer.launches[k] ? timer.total_ms[k] / (double)timer.launches[k] : 0.0;
+            bytes[k] = timer.bytes[k];
+            std::memset(names + 32 * k, 0, 32);
+            std::strncpy(names + 32 * k, timer.names[k] ? timer.names[k] : "?", 31);
+        }
+    }
+    timer.destroy();
+    HIPCHK(e);
+    for (int b = 0; b < B; ++b)
+        if (hs[b].done) {
+            set_error("the instrumented iteration finished early (non-finite or line search)");
+            return GPE_ENONFINITE;
+        }
+    return n;
+}
+
 Geo instance_geo(const Geo&, const gpe_problem_t& p) { return make_geo(p); }
 
 // Solve B instances of one grid.  Inputs phi[b], V[b] are device fields in the caller's type
@@ -238,64 +321,57 @@ int gpe_pcg_profile(gpe_plan_t* plan, const void* V, const void* phi, const gpe_
     int st = validate_opts(opts);
     if (st != GPE_OK) return st;
     if (iters < 1 || cap < 1) { set_error("iters and cap must be >= 1"); return GPE_EINVAL; }
-    hipStream_t s = (hipStream_t)stream;
-    const Geo& g = plan->g;
-    const int64_t N = g.N;
-    HIPCHK(reduce_init(plan->red, 1, R_COUNT, std::max<size_t>(1 << 18, R_COUNT * region_doubles_for(g, 1))));
-    HIPCHK(plan->scal.ensure(3 * sizeof(Scal)));
-    gpe_pcg_opts_t o = *opts;
-    o.tol_res_inf = 0.0;
-    o.tol_energy = 0.0;
-    o.max_iter = (int64_t)iters + 1000;
-    std::vector<Scal> hs(1, make_scal(plan->prob, g, o));
-    PhaseArgs pa;
-    pa.g = g;
-    pa.B = 1;
-    pa.tw = &plan->tw;
-    pa.S = (Scal*)plan->scal.ptr;
-    pa.red = &plan->red;
-    pa.region_doubles = region_doubles_for(g, 1);
-    pa.precond = o.precond;
-    pa.check_every = 1;
-    pa.refresh_every = 0;
-    pa.final_f_r_is_rp = false;
-    KernelTimer timer;
-    hipError_t e = timer.init();
-    const bool fp32 = !plan->f64() || o.precision == 1;
-    if (e == hipSuccess) {
-        if (fp32) {
-            IterFields<float> f = carve_fields<float>(plan->f64() ? plan->solver32 : plan->solver, N, &e);
-            if (e == hipSuccess) {
-                if (plan->f64()) {
-                    e = convert_complex(false, phi, f.phi, N, s);
-                    if (e == hipSuccess) e = convert_real(false, V, f.V, N, s);
-                } else {
-                    e = copy_bytes(phi, f.phi, sizeof(float) * 2 * N, s);
-                    if (e == hipSuccess) e = copy_bytes(V, f.V, sizeof(float) * N, s);
-                }
+    const void* Vs[1] = {V};
+    const void* phis[1] = {phi};
+    ProfileWork w{plan->g, &plan->tw, &plan->red, &plan->scal, &plan->solver, &plan->solver32};
+    return profile_group(w, 1, &plan->prob, plan->f64(), Vs, phis, *opts, iters, cap, avg_ms, bytes, names,
+                         (hipStream_t)stream);
+}
+
+int gpe_pcg_profile_batched(int count, const gpe_problem_t* probs, int dtype, const void* const* V,
+                            const void* const* phi, const gpe_pcg_opts_t* opts, int iters, int cap, double* avg_ms,
+                            double* bytes, char* names, void* stream) {
+    if (count < 1 || !probs || !V || !phi || !avg_ms || !bytes || !names) {
+        set_error("invalid batch arguments");
+        return GPE_EINVAL;
+    }
+    if (dtype != GPE_F64 && dtype != GPE_F32) { set_error("dtype must be GPE_F64 or GPE_F32"); return GPE_EINVAL; }
+    int st = validate_opts(opts);
+    if (st != GPE_OK) return st;
+    if (iters < 1 || cap < 1) { set_error("iters and cap must be >= 1"); return GPE_EINVAL; }
+    for (int i = 0; i < count; ++i) {
+        if ((st = validate_problem(&probs[i])) != GPE_OK) return st;
+        if (!V[i] || !phi[i]) { set_error("NULL field in batch"); return GPE_EINVAL; }
+        for (int a = 0; a < 3; ++a)
+            if (probs[i].dim != probs[0].dim || (a < probs[0].dim && probs[i].n[a] != probs[0].n[a])) {
+                set_error("a profiled batch must share one grid");
+                return GPE_EINVAL;
             }
-            if (e == hipSuccess) e = profile_phase<float>(pa, f, hs, iters, timer, s);
-        } else {
-            IterFields<double> f = carve_fields<double>(plan->solver, N, &e);
-            if (e == hipSuccess) e = copy_bytes(phi, f.phi, sizeof(double) * 2 * N, s);
-            if (e == hipSuccess) e = copy_bytes(V, f.V, sizeof(double) * N, s);
-            if (e == hipSuccess) e = profile_phase<double>(pa, f, hs, iters, timer, s);
-        }
     }
-    int n = 0;
-    if (e == hipSuccess) {
-        n = std::min(timer.slots, cap);
-        for (int k = 0; k < n; ++k) {
-            avg_ms[k] = timer.launches[k] ? timer.total_ms[k] / (double)timer.launches[k] : 0.0;
-            bytes[k] = timer.bytes[k];
-            std::memset(names + 32 * k, 0, 32);
-            std::strncpy(names + 32 * k, timer.names[k] ? timer.names[k] : "?", 31);
-        }
+    const Geo g = make_geo(probs[0]);
+    Twiddles tw;
+    Reduce red;
+    DevBuf scal, f64, f32;
+    hipError_t e = build_twiddles(g, tw);
+    if (e != hipSuccess) {
+        set_error(std::string("twiddle tables: ") + hipGetErrorString(e));
+        return GPE_EHIP;
     }
-    timer.destroy();
-    HIPCHK(e);
-    if (hs[0].done) { set_error("the instrumented iteration finished early (non-finite or line search)"); return GPE_ENONFINITE; }
-    return n;
+    ProfileWork w{g, &tw, &red, &scal, &f64, &f32};
+    st = profile_group(w, count, probs, dtype == GPE_F64, V, phi, *opts, iters, cap, avg_ms, bytes, names,
+                       (hipStream_t)stream);
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    for (int a = 0; a < 3; ++a) {
+        tw.t64[a].release();
+        tw.t32[a].release();
+    }
+    red.parts.release();
+    red.counters.release();
+    red.scalars.release();
+    scal.release();
+    f64.release();
+    f32.release();
+    return st;
 }
 
 int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void* const* V, void* const* phi_inout,

@@ -9,6 +9,19 @@
 
 namespace gpe {
 
+// Compute units of the current device (queried once per device).
+inline int device_cus() {
+    static int cached[16] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 256;
+    if (cached[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
 // Optional start/stop events a launch records around its own execution (per-kernel timing).
 struct LaunchEvents {
     hipEvent_t start, stop;
@@ -80,16 +93,20 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
     // reduction scratch sized for the pass's own sums and for absorbing up to 16 sums of its predecessor
     const size_t lds = pass_lds_bytes<T>(g.n[AX], C, threads, Op::K > 16 ? Op::K : 16);
     if (threads > kMaxPassThreads) return hipErrorInvalidConfiguration;
-    auto kern = pass_kernel<T, AX, Op, kMaxPassThreads>;
-    static bool attr_set = false;  // one attribute call per instantiation
+    const int64_t blocks = nb * (int64_t)B;
+    // one workgroup per CU or fewer: fetch everything ahead of the scalar logic (see pass_kernel)
+    const bool early = blocks <= device_cus();
+    auto kern = early ? pass_kernel<T, AX, Op, kMaxPassThreads, true> : pass_kernel<T, AX, Op, kMaxPassThreads, false>;
+    static bool attr_set = false;  // one attribute call per instantiation pair
     if (!attr_set) {
         // Raise the dynamic-LDS cap once; a runtime that does not need it may refuse harmlessly.
-        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPassLdsBudget) !=
-            hipSuccess)
-            (void)hipGetLastError();
+        for (auto k : {pass_kernel<T, AX, Op, kMaxPassThreads, true>, pass_kernel<T, AX, Op, kMaxPassThreads, false>})
+            if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPassLdsBudget) !=
+                hipSuccess)
+                (void)hipGetLastError();
         attr_set = true;
     }
-    launch_timed(ev, kern, dim3((unsigned)(nb * (int64_t)B)), dim3(threads), lds, s, g, C, (const C2<T>*)tw, op, pr);
+    launch_timed(ev, kern, dim3((unsigned)blocks), dim3(threads), lds, s, g, C, (const C2<T>*)tw, op, pr);
     return hipGetLastError();
 }
 

@@ -147,7 +147,8 @@ constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 //   static constexpr bool SCALARS;   (bit k of MAXMASK set: sum k is a max-reduction)
 //   static constexpr bool PREFETCH;
 //   struct State;
-//   __device__ void prefetch(const Geo&, const LineCtx&, State&) const;                   // if PREFETCH
+//   __device__ void prefetch(const Geo&, const LineCtx&, State&) const;       // if PREFETCH: load()'s inputs
+//   __device__ void prefetch_tail(const Geo&, const LineCtx&, State&) const;  // if PREFETCH: store()'s inputs
 //   struct Intake;                                                                         // if SCALARS
 //   __device__ void intake(int b, Intake&) const;                                          // if SCALARS
 //   __device__ void begin(const Geo&, int b, int blk_in_inst, double* red, Scal* s, Intake&) const;  // if SCALARS
@@ -156,7 +157,7 @@ constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 //                            C2<T>* buf, const C2<T>* tw) const;   (buf/tw: to transform more lines)
 //   __device__ void store(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
 // K sums are accumulated per thread in FP64 and reduced deterministically into pr.parts.
-template <typename T, int AX, class Op, int MAXT>
+template <typename T, int AX, class Op, int MAXT, bool EARLY>
 __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op,
                                                     Partials pr) {
     extern __shared__ double4 smem_raw[];
@@ -172,27 +173,45 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
     // The loads of the scalar state and of the producers' partial rows go first, then every load
     // that does not depend on the state (twiddles, fields): all complete in one round trip, and
     // begin() waits for the first group only (memory counters retire in issue order).
+    // EARLY (launches too small to fill the chip, bound by latency): twiddles and every field,
+    // epilogue inputs included, are fetched before begin().  Otherwise (many workgroups per CU,
+    // bound by bandwidth) they are fetched when needed, which keeps the register footprint and
+    // hence the occupancy that hides the latency.
     typename IntakeOf<Op>::type in;
     if constexpr (Op::SCALARS) op.intake(lc.b, in);
     // (four named registers rather than an array, which the compiler may demote to scratch)
     auto tw_at = [&](int j) { return min((int)(threadIdx.x + j * blockDim.x), lc.M - 1); };
-    const C2<T> tw0 = twg[tw_at(0)], tw1 = twg[tw_at(1)], tw2 = twg[tw_at(2)], tw3 = twg[tw_at(3)];
-    if constexpr (Op::PREFETCH) op.prefetch(g, lc, st);
+    C2<T> tw0, tw1, tw2, tw3;
+    if constexpr (EARLY) {
+        tw0 = twg[tw_at(0)];
+        tw1 = twg[tw_at(1)];
+        tw2 = twg[tw_at(2)];
+        tw3 = twg[tw_at(3)];
+        if constexpr (Op::PREFETCH) {
+            op.prefetch(g, lc, st);
+            op.prefetch_tail(g, lc, st);
+        }
+    }
     if constexpr (Op::SCALARS) {
         __shared__ Scal s_local;
         op.begin(g, lc.b, blk_in_inst, red, &s_local, in);  // all threads; ends with a barrier
         if (s_local.done) return;                       // uniform per block (one instance per block)
         lc.sc = &s_local;
     }
-    auto tw_put = [&](int j, C2<T> x) {
-        const int i = threadIdx.x + j * blockDim.x;
-        if (i < lc.M) tw[i] = x;
-    };
-    tw_put(0, tw0);
-    tw_put(1, tw1);
-    tw_put(2, tw2);
-    tw_put(3, tw3);
-    for (int i = threadIdx.x + kTwiddleRegs * blockDim.x; i < lc.M; i += blockDim.x) tw[i] = twg[i];
+    if constexpr (EARLY) {
+        auto tw_put = [&](int j, C2<T> x) {
+            const int i = threadIdx.x + j * blockDim.x;
+            if (i < lc.M) tw[i] = x;
+        };
+        tw_put(0, tw0);
+        tw_put(1, tw1);
+        tw_put(2, tw2);
+        tw_put(3, tw3);
+        for (int i = threadIdx.x + kTwiddleRegs * blockDim.x; i < lc.M; i += blockDim.x) tw[i] = twg[i];
+    } else {
+        for (int i = threadIdx.x; i < lc.M; i += blockDim.x) tw[i] = twg[i];
+        if constexpr (Op::PREFETCH) op.prefetch(g, lc, st);
+    }
     __syncthreads();
 
     C2<T> v[8];
@@ -204,6 +223,7 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
     if (Op::FWD) fft_line<T, -1>(v, buf, tw, lc.t, lc.lg);
     op.spectral(g, lc, st, v, acc, buf, tw);
     if (Op::INV) fft_line<T, +1>(v, buf, tw, lc.t, lc.lg);
+    if constexpr (!EARLY && Op::PREFETCH) op.prefetch_tail(g, lc, st);
     op.store(g, lc, st, v, acc);
 
     if constexpr (Op::K > 0) {

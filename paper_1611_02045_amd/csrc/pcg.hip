@@ -446,6 +446,7 @@ struct OpResid {
             st.V[q] = f.V[i];
         }
     }
+    __device__ void prefetch_tail(const Geo&, const LineCtx&, State&) const {}
     __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s, Intake& it) const {
         begin_step(Sin, Sout, pb, b, blk, red, s, it);
     }
@@ -526,6 +527,7 @@ struct OpPMid {
 #pragma unroll
         for (int q = 0; q < 8; ++q) st.w[q] = w[lc.at(q)];
     }
+    __device__ void prefetch_tail(const Geo&, const LineCtx&, State&) const {}
     __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s, Intake& it) const {
         if constexpr (ABS) {
             __shared__ double tot[A_K];
@@ -579,16 +581,19 @@ struct OpPLast {
     IterFields<T> f;
     const Scal* Sin;  // S_res
     int post;
-    // every input is fetched ahead: w for the transform, and what the epilogue and the CG sums read
+    // w for the transform; the tail: what the epilogue and the CG sums read
     struct State {
         C2<T> w[8], ph[8], r[8], rp[8], pp[8];
         T V[8];
     };
     __device__ void prefetch(const Geo&, const LineCtx& lc, State& st) const {
 #pragma unroll
+        for (int q = 0; q < 8; ++q) st.w[q] = f.w[lc.at(q)];
+    }
+    __device__ void prefetch_tail(const Geo&, const LineCtx& lc, State& st) const {
+#pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
-            st.w[q] = f.w[i];
             st.ph[q] = f.phi[i];
             st.V[q] = f.V[i];
             st.r[q] = f.r[i];
@@ -648,14 +653,20 @@ struct OpLp {
         C2<T> w[FIRST ? 1 : 8];
         T V[LAST ? 8 : 1];
     };
-    // phi (when read), P r (FIRST, from which load() builds the new direction) or p, and what the
-    // epilogue adds: the previous passes' partial L phat (w) and V
+    // phi (when read) and P r (FIRST, from which load() builds the new direction) or p; the tail:
+    // what the epilogue adds, the previous passes' partial L phat (w) and V
     __device__ void prefetch(const Geo&, const LineCtx& lc, State& st) const {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
             if constexpr (PHI) st.ph[q] = f.phi[i];
             st.p[q] = FIRST ? f.pr[i] : f.pp[i];
+        }
+    }
+    __device__ void prefetch_tail(const Geo&, const LineCtx& lc, State& st) const {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = lc.at(q);
             if constexpr (!FIRST) st.w[q] = f.w[i];
             if constexpr (LAST) st.V[q] = f.V[i];
         }

@@ -72,6 +72,9 @@ SIGNATURES = {
     "gpe_adjoint_param_grads": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), _VP]),
     "gpe_pcg_profile": (_I, [_VP, _VP, _VP, ctypes.POINTER(PcgOpts), _I, _I, ctypes.POINTER(_D),
                              ctypes.POINTER(_D), ctypes.c_char_p, _VP]),
+    "gpe_pcg_profile_batched": (_I, [_I, ctypes.POINTER(Problem), _I, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                     ctypes.POINTER(PcgOpts), _I, _I, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                     ctypes.c_char_p, _VP]),
     "gpe_last_error": (ctypes.c_char_p, []),
     "gpe_version": (ctypes.c_char_p, []),
 }
@@ -282,8 +285,7 @@ class Plan:
         return gV, db.value, do.value
 
 
-def pcg_solve_batched(problems, Vs, phis, dtype: str = "f64", stream=None, **opts):
-    """Independent solves of several problems in one iteration loop (fields updated in place)."""
+def _batch_args(problems, Vs, phis, dtype):
     count = len(problems)
     P = (Problem * count)(*[make_problem(p.dim, p.n, p.L, p.beta, p.omega) for p in problems])
     want_c = torch.complex128 if dtype == "f64" else torch.complex64
@@ -296,6 +298,26 @@ def pcg_solve_batched(problems, Vs, phis, dtype: str = "f64", stream=None, **opt
             raise ValueError("field dtype/shape does not match its problem")
     vp = (ctypes.c_void_p * count)(*[V.data_ptr() for V in Vs])
     pp = (ctypes.c_void_p * count)(*[phi.data_ptr() for phi in phis])
+    return count, P, vp, pp
+
+
+def pcg_profile_batched(problems, Vs, phis, dtype: str = "f64", iters: int = 20, stream=None, **opts):
+    """Per-kernel timings of `iters` iterations of the instances solved together: (name, avg_ms, bytes)."""
+    count, P, vp, pp = _batch_args(problems, Vs, phis, dtype)
+    o = default_opts(**opts)
+    cap = 16
+    ms = (ctypes.c_double * cap)()
+    by = (ctypes.c_double * cap)()
+    names = ctypes.create_string_buffer(32 * cap)
+    n = _check(lib().gpe_pcg_profile_batched(count, P, F64 if dtype == "f64" else F32, vp, pp, ctypes.byref(o),
+                                             int(iters), cap, ms, by, names, _stream(stream)))
+    raw = names.raw
+    return [(raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode(), ms[k], by[k]) for k in range(n)]
+
+
+def pcg_solve_batched(problems, Vs, phis, dtype: str = "f64", stream=None, **opts):
+    """Independent solves of several problems in one iteration loop (fields updated in place)."""
+    count, P, vp, pp = _batch_args(problems, Vs, phis, dtype)
     o = default_opts(**opts)
     reps = (PcgReport * count)()
     st = lib().gpe_pcg_solve_batched(count, P, F64 if dtype == "f64" else F32, vp, pp, ctypes.byref(o), reps,

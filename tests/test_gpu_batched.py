@@ -106,3 +106,30 @@ def test_sweep_instances_sample(torch_gpu):
         r, lam = O.residual(bi.prob, bi.V, got)
         assert float(np.max(np.abs(r))) <= 1.5e-8
         assert abs(O.energy(bi.prob, bi.V, got) - rep["E"]) < 1e-10 * abs(rep["E"])
+
+
+def test_batched_profile_counts_every_instance(torch_gpu):
+    """gpe_pcg_profile_batched times the same kernels as the single-instance profile, with the
+    algorithmic bytes of all instances, and leaves the inputs unchanged; mixed grids are refused."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    probs = [Problem(2, (64, 64), (8.0, 8.0), 100.0, 0.5), Problem(2, (64, 64), (7.0, 7.0), 60.0, 0.3)]
+    Vs = [torch.from_numpy(harmonic_potential(p)).to("cuda") for p in probs]
+    phis = [torch.from_numpy(vortex_seed_2d(p, 40 + k)).to("cuda") for k, p in enumerate(probs)]
+    before = [x.clone() for x in phis]
+    single = gpe.Plan.from_problem(probs[0], "f64").profile(Vs[0], phis[0], iters=3, precision="fp64")
+    for precision in ("fp64", "mixed"):
+        prof = gpe.pcg_profile_batched(probs, Vs, phis, "f64", iters=3, precision=precision)
+        assert [n for n, _, _ in prof] == [n for n, _, _ in single]
+        for (_, ms, by), (_, _, by1) in zip(prof, single):
+            assert ms > 0.0
+            scale = 2.0 if precision == "fp64" else 1.0  # FP32 fields: half the bytes per instance
+            assert by == pytest.approx(scale * by1)
+    for a, b in zip(phis, before):
+        assert torch.equal(a, b)
+    odd = [probs[0], Problem(2, (32, 32), (8.0, 8.0), 100.0, 0.5)]
+    oddV = [Vs[0], torch.from_numpy(harmonic_potential(odd[1])).to("cuda")]
+    oddphi = [phis[0], torch.from_numpy(vortex_seed_2d(odd[1], 7)).to("cuda")]
+    with pytest.raises(gpe.GpeError) as ei:
+        gpe.pcg_profile_batched(odd, oddV, oddphi, "f64", iters=2)
+    assert ei.value.status == -1
