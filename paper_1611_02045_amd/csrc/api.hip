@@ -27,6 +27,7 @@ Geo make_geo(const gpe_problem_t& p) {
             g.lg[a] = lg;
             g.L[a] = p.L[a];
             g.h[a] = 2.0 * p.L[a] / p.n[a];
+            g.dk[a] = 3.141592653589793238462643383279502884 / p.L[a];
             g.cell *= g.h[a];
             g.N *= p.n[a];
         } else {
@@ -34,6 +35,7 @@ Geo make_geo(const gpe_problem_t& p) {
             g.lg[a] = 0;
             g.L[a] = 1.0;
             g.h[a] = 1.0;
+            g.dk[a] = 3.141592653589793238462643383279502884;
         }
     }
     return g;

@@ -41,14 +41,16 @@ struct Geo {
     int lg[3];      // log2 n
     double L[3];    // half-widths
     double h[3];    // spacings 2L/n
+    double dk[3];   // frequency spacings pi/L
     double cell;    // h^d
     int64_t N;      // points per field
 };
 
-// Frequency xi of transform index j on an axis of n points and half-width L (Nyquist kept).
-__device__ __forceinline__ double freq_of(int j, int n, double L) {
+// Frequency xi of transform index j on an axis of n points and half-width L (Nyquist kept), given
+// the spacing dk = pi/L.
+__device__ __forceinline__ double freq_of(int j, int n, double dk) {
     int p = (j < (n >> 1)) ? j : j - n;
-    return (double)p * (3.141592653589793238462643383279502884 / L);
+    return (double)p * dk;
 }
 // Grid coordinate x_k = -L + k h.
 __device__ __forceinline__ double coord_of(int k, double L, double h) { return -L + (double)k * h; }
@@ -59,7 +61,7 @@ __device__ __forceinline__ double coord_of(int k, double L, double h) { return -
 struct alignas(16) Scal {
     // problem parameters (per instance: batched solves mix boxes, beta and omega)
     double beta, omega, cell;
-    double L[3], h[3];
+    double L[3], h[3], dk[3];  // dk = pi/L
     // scalars of the current iterate phi_n
     double a;          // <phi, L phi>, L = T + V - omega L_z (tracked field)
     double aR;         // <phi, R phi>, R = -omega L_z

@@ -9,12 +9,13 @@
 // multiplier can be applied in registers and an inverse transform can follow with no LDS round
 // trip in between, and the inverse returns each thread the very positions it loaded -- so
 // pointwise epilogues see the original input in registers.  Between stages the data goes
-// through a padded LDS line buffer (one write, barrier, one read, barrier).
+// through a padded LDS line buffer (one write, barrier, one read, barrier; the barriers are
+// wave-level when each line lies within one wave).
 //
 // The forward transform is unnormalised, sum_j x_j e^{-2 pi i jk/M}; the inverse uses e^{+...}
 // and is also unnormalised (callers fold 1/M into their multiplier), matching the expansions
 // of Section 3 of the paper.  Twiddles come from an LDS table tw[e] = exp(-2 pi i e/M) built
-// from FP64 host values.
+// from FP64 host values (three per radix-8 stage; the other four are products of two of them).
 #pragma once
 
 #include "common.hpp"
@@ -23,8 +24,16 @@ namespace gpe {
 
 // Padded LDS index: one spare slot per 8 points spreads the stride-Ns Stockham writes over banks.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
-// Padded length of one LDS line (odd, so neighbouring lines start in different banks).
-__host__ __device__ constexpr int line_stride(int M) { return M + (M >> 3) + 1; }
+// Padded length (in points) of one LDS line of a workgroup holding C lines.  x passes keep each
+// line in consecutive lanes, and an odd length starts neighbouring lines in different banks.
+// Strided passes interleave their lines lane by lane (lane = line + C t); with U = 16 (8-byte
+// points) or 8 (16-byte points) points per LDS cycle, a length of U/C mod U points puts the U
+// lanes served together on distinct banks in every exchange.
+__host__ __device__ constexpr int line_stride(int M, int point_bytes = 8, int axis = 0, int C = 1) {
+    const int U = point_bytes == 8 ? 16 : 8;
+    const int pad = C >= U ? 1 : U / C;
+    return axis == 0 ? M + (M >> 3) + 1 : ((M + (M >> 3) + U - 1) & ~(U - 1)) + pad;
+}
 
 // a * (DIR * i)
 template <typename T, int DIR>
@@ -73,19 +82,39 @@ __host__ __device__ __forceinline__ void dft8(C2<T> (&v)[8]) {
     v[1] = b0; v[3] = b1; v[5] = b2; v[7] = b3;
 }
 
-// Read back v[s] = buf[t + s*TPL] after a stage's scattered write; barriers on both sides.
+// Order this wave's LDS accesses (a wave's LDS operations execute in issue order; the fences keep
+// the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Read back v[s] = buf[t + s*TPL] after a stage's scattered write, synchronised on both sides:
+// across the workgroup, or only within the wave when every line lies inside one wave (`wave`).
+// For TPL >= 8, lpad(t + s*TPL) = lpad(t) + s*lpad(TPL): one base and one stride.
 template <typename T>
-__device__ __forceinline__ void exchange_read(C2<T> (&v)[8], const C2<T>* buf, int t, int TPL) {
-    __syncthreads();
+__device__ __forceinline__ void exchange_read(C2<T> (&v)[8], const C2<T>* buf, int t, int TPL, bool wave) {
+    if (wave) wave_lds_sync(); else __syncthreads();
+    if (TPL >= 8) {
+        const C2<T>* p = buf + lpad(t);
+        const int st = lpad(TPL);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) v[s] = buf[lpad(t + s * TPL)];
-    __syncthreads();
+        for (int s = 0; s < 8; ++s) v[s] = p[s * st];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = buf[lpad(t + s * TPL)];
+    }
+    if (wave) wave_lds_sync(); else __syncthreads();
 }
 
 // Full line transform (see file comment).  All threads of the block must call it with the same
-// lg; `buf` is this thread's line region in LDS (line_stride(M) entries) and `tw` the table.
+// lg and `wave`; `buf` is this thread's line region in LDS (one padded line) and `tw` the
+// table.  wave: each line is held by threads of a single wave (lines of at most 512 points laid
+// along consecutive lanes), so the exchanges need no workgroup barrier.
 template <typename T, int DIR>
-__device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, int t, int lg) {
+__device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, int t, int lg,
+                                         bool wave = false) {
     const int TPL = 1 << (lg - 3);
     const int rem = lg % 3;
     const int n8 = lg / 3;
@@ -100,7 +129,7 @@ __device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>*
             buf[lpad(2 * j)] = v[q];
             buf[lpad(2 * j + 1)] = v[q + 4];
         }
-        exchange_read(v, buf, t, TPL);
+        exchange_read(v, buf, t, TPL, wave);
         lgNs = 1;
     } else if (rem == 2) {
         // radix-4 stage at Ns = 1: butterflies j = t on v[0,2,4,6] and j = t + TPL on v[1,3,5,7]
@@ -111,30 +140,117 @@ __device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>*
             buf[lpad(4 * t + r)] = v[2 * r];
             buf[lpad(4 * (t + TPL) + r)] = v[2 * r + 1];
         }
-        exchange_read(v, buf, t, TPL);
+        exchange_read(v, buf, t, TPL, wave);
         lgNs = 2;
     }
     for (int k = 0; k < n8; ++k) {
         // radix-8 stage at Ns = 2^lgNs: butterfly j = t on v[r] (positions t + r*TPL)
         if (lgNs > 0) {
+            // w_r = tw[r * step]: w1, w2, w4 from the table, the other four as products of two
             const int jm = t & ((1 << lgNs) - 1);
             const int step = jm << (lg - 3 - lgNs);  // jm * M / (8 Ns)
-#pragma unroll
-            for (int r = 1; r < 8; ++r) {
-                C2<T> w = tw[r * step];
-                if (DIR > 0) w.y = -w.y;
-                v[r] = mul(v[r], w);
+            C2<T> w1 = tw[step], w2 = tw[2 * step], w4 = tw[4 * step];
+            if (DIR > 0) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+                w4.y = -w4.y;
             }
+            const C2<T> w3 = mul(w1, w2);
+            v[1] = mul(v[1], w1);
+            v[2] = mul(v[2], w2);
+            v[3] = mul(v[3], w3);
+            v[4] = mul(v[4], w4);
+            v[5] = mul(v[5], mul(w1, w4));
+            v[6] = mul(v[6], mul(w2, w4));
+            v[7] = mul(v[7], mul(w3, w4));
         }
         dft8<T, DIR>(v);
         if (k + 1 < n8) {
             const int Ns = 1 << lgNs;
             const int base = ((t >> lgNs) << (lgNs + 3)) + (t & (Ns - 1));
+            if (Ns == 1 || Ns >= 8) {
+                // base + r*Ns never crosses a multiple of 8 for Ns = 1 (base = 8t) and keeps
+                // base's offset within its group of 8 for Ns >= 8: lpad is affine in r
+                C2<T>* p = buf + lpad(base);
+                const int st = Ns == 1 ? 1 : lpad(Ns);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) buf[lpad(base + r * Ns)] = v[r];
-            exchange_read(v, buf, t, TPL);
+                for (int r = 0; r < 8; ++r) p[r * st] = v[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) buf[lpad(base + r * Ns)] = v[r];
+            }
+            exchange_read(v, buf, t, TPL, wave);
         }
         lgNs += 3;
+    }
+}
+
+// fft_line for a compile-time size 2^LG: the same stages, with every stride, offset and stage
+// count a constant (LDS addresses become immediate offsets).  WAVE: lines lie within one wave.
+template <typename T, int DIR, int LG, bool WAVE>
+__device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, int t) {
+    static_assert(LG >= 3 && LG <= 10, "lines of 8 to 1024 points");
+    constexpr int TPL = 1 << (LG - 3);
+    constexpr int REM = LG % 3;
+    constexpr int N8 = LG / 3;
+    auto sync = [] {
+        if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
+    };
+    auto read_back = [&] {
+        sync();
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = buf[lpad(t + s * TPL)];
+        sync();
+    };
+    if constexpr (REM == 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dft2<T, DIR>(v[q], v[q + 4]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = t + q * TPL;
+            buf[lpad(2 * j)] = v[q];
+            buf[lpad(2 * j + 1)] = v[q + 4];
+        }
+        read_back();
+    } else if constexpr (REM == 2) {
+        dft4<T, DIR>(v[0], v[2], v[4], v[6]);
+        dft4<T, DIR>(v[1], v[3], v[5], v[7]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            buf[lpad(4 * t + r)] = v[2 * r];
+            buf[lpad(4 * (t + TPL) + r)] = v[2 * r + 1];
+        }
+        read_back();
+    }
+#pragma unroll
+    for (int k = 0; k < N8; ++k) {
+        const int lgNs = REM + 3 * k;
+        const int Ns = 1 << lgNs;
+        if (lgNs > 0) {
+            const int jm = t & (Ns - 1);
+            const int step = jm << (LG - 3 - lgNs);
+            C2<T> w1 = tw[step], w2 = tw[2 * step], w4 = tw[4 * step];
+            if (DIR > 0) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+                w4.y = -w4.y;
+            }
+            const C2<T> w3 = mul(w1, w2);
+            v[1] = mul(v[1], w1);
+            v[2] = mul(v[2], w2);
+            v[3] = mul(v[3], w3);
+            v[4] = mul(v[4], w4);
+            v[5] = mul(v[5], mul(w1, w4));
+            v[6] = mul(v[6], mul(w2, w4));
+            v[7] = mul(v[7], mul(w3, w4));
+        }
+        dft8<T, DIR>(v);
+        if (k + 1 < N8) {
+            const int base = ((t >> lgNs) << (lgNs + 3)) + (t & (Ns - 1));
+#pragma unroll
+            for (int r = 0; r < 8; ++r) buf[lpad(base + r * Ns)] = v[r];
+            read_back();
+        }
     }
 }
 

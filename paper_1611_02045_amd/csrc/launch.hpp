@@ -42,8 +42,8 @@ constexpr size_t kPassLdsBudget = 96 * 1024;
 // to 256 VGPRs per lane without scratch spills.
 constexpr int kMaxPassThreads = 256;
 
-inline size_t pass_lds_bytes_cb(int cb, int M, int C, int threads, int K) {
-    size_t b = (size_t)cb * ((size_t)M + (size_t)C * line_stride(M));
+inline size_t pass_lds_bytes_cb(int cb, int M, int C, int threads, int K, int axis) {
+    size_t b = (size_t)cb * ((size_t)M + (size_t)C * line_stride(M, cb, axis, C));
     b = (b + 15) & ~(size_t)15;
     b += sizeof(double) * (size_t)((((threads + 63) / 64) + 1) * (K > 0 ? K : 1) + 4);
     return b;
@@ -71,7 +71,7 @@ inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes, int B =
     while (C > 1 && lines / C < 64) C >>= 1;
     while (C > 1 && (lpf % C) != 0) C >>= 1;
     // keep the LDS footprint (twiddles + lines + reduction scratch) within budget
-    while (C > 1 && pass_lds_bytes_cb(complex_bytes, g.n[AX], C, C * TPL, 32) > kPassLdsBudget) C >>= 1;
+    while (C > 1 && pass_lds_bytes_cb(complex_bytes, g.n[AX], C, C * TPL, 32, AX) > kPassLdsBudget) C >>= 1;
     return C;
 }
 
@@ -91,16 +91,24 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
     pr.nb = nb;
     if (pr.stride == 0) pr.stride = nb;
     // reduction scratch sized for the pass's own sums and for absorbing up to 16 sums of its predecessor
-    const size_t lds = pass_lds_bytes<T>(g.n[AX], C, threads, Op::K > 16 ? Op::K : 16);
+    const size_t lds = pass_lds_bytes<T>(g.n[AX], C, threads, Op::K > 16 ? Op::K : 16, AX);
     if (threads > kMaxPassThreads) return hipErrorInvalidConfiguration;
     const int64_t blocks = nb * (int64_t)B;
     // one workgroup per CU or fewer: fetch everything ahead of the scalar logic (see pass_kernel)
     const bool early = blocks <= device_cus();
-    auto kern = early ? pass_kernel<T, AX, Op, kMaxPassThreads, true> : pass_kernel<T, AX, Op, kMaxPassThreads, false>;
-    static bool attr_set = false;  // one attribute call per instantiation pair
+    // lines of 512 points (the common size) take the compile-time transform
+    constexpr int kLG = 9;
+    const bool ct = g.lg[AX] == kLG;
+    using K = decltype(&pass_kernel<T, AX, Op, kMaxPassThreads, true, 0>);
+    const K variants[4] = {pass_kernel<T, AX, Op, kMaxPassThreads, false, 0>,
+                           pass_kernel<T, AX, Op, kMaxPassThreads, true, 0>,
+                           pass_kernel<T, AX, Op, kMaxPassThreads, false, kLG>,
+                           pass_kernel<T, AX, Op, kMaxPassThreads, true, kLG>};
+    const K kern = variants[(ct ? 2 : 0) + (early ? 1 : 0)];
+    static bool attr_set = false;  // one attribute call per instantiation set
     if (!attr_set) {
         // Raise the dynamic-LDS cap once; a runtime that does not need it may refuse harmlessly.
-        for (auto k : {pass_kernel<T, AX, Op, kMaxPassThreads, true>, pass_kernel<T, AX, Op, kMaxPassThreads, false>})
+        for (K k : variants)
             if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPassLdsBudget) !=
                 hipSuccess)
                 (void)hipGetLastError();

@@ -44,10 +44,10 @@ struct OpApply {
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
                              const C2<T>*) const {
         const double rot = rot_coef<AX>(g, lc, omega);
-        const double inv = 1.0 / lc.M;
+        const double inv = ldexp(1.0, -lc.lg);  // 1/M, exact
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const double xi = freq_of(lc.k(s), lc.M, g.L[AX]);
+            const double xi = freq_of(lc.k(s), lc.M, g.dk[AX]);
             v[s] = scl(v[s], (T)((0.5 * kin * xi * xi + rot * xi) * inv));
         }
     }
@@ -135,10 +135,10 @@ struct OpEnergy {
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[4], C2<T>*,
                              const C2<T>*) const {
         const double rot = rot_coef<AX>(g, lc, omega);
-        const double inv = 1.0 / lc.M;
+        const double inv = ldexp(1.0, -lc.lg);  // 1/M, exact
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const double xi = freq_of(lc.k(s), lc.M, g.L[AX]);
+            const double xi = freq_of(lc.k(s), lc.M, g.dk[AX]);
             const double w = (double)abs2(v[s]) * inv;
             acc[0] += 0.5 * xi * xi * w;
             acc[1] += rot * xi * w;
@@ -260,17 +260,17 @@ struct OpPre {
         // frequencies of the other (already transformed) axes
         double ko = 0.0;
         if (AX == 1) {
-            const double xi = freq_of(lc.i1, g.n[0], g.L[0]);
+            const double xi = freq_of(lc.i1, g.n[0], g.dk[0]);
             ko = xi * xi;
         } else if (AX == 2) {
-            const double xi = freq_of(lc.i1, g.n[0], g.L[0]);
-            const double mu = freq_of(lc.i2, g.n[1], g.L[1]);
+            const double xi = freq_of(lc.i1, g.n[0], g.dk[0]);
+            const double mu = freq_of(lc.i2, g.n[1], g.dk[1]);
             ko = xi * xi + mu * mu;
         }
-        const double invN = 1.0 / (double)g.N;
+        const double invN = ldexp(1.0, -(g.lg[0] + g.lg[1] + g.lg[2]));  // 1/N, exact
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const double k = freq_of(lc.k(s), lc.M, g.L[AX]);
+            const double k = freq_of(lc.k(s), lc.M, g.dk[AX]);
             v[s] = scl(v[s], (T)(invN / (a + 0.5 * (ko + k * k))));
         }
     }

@@ -30,6 +30,7 @@ struct LineCtx {
     int64_t stride; // distance between consecutive points of the line
     int64_t off_b;  // b * N
     const Scal* sc; // the instance's scalar state in LDS (solver passes only)
+    bool wave;      // every line of the workgroup lies within one wave (x passes, M <= 512)
     __device__ __forceinline__ int64_t at(int s) const { return base + (int64_t)(t + s * TPL) * stride; }
     __device__ __forceinline__ int k(int s) const { return t + s * TPL; }
 };
@@ -42,12 +43,13 @@ __host__ __device__ inline int64_t lines_per_field(const Geo& g, int AX) {
 // Every extent is a power of two, so the decomposition of the launch into lines uses shifts and
 // masks only (64-bit integer division is a long software sequence on the GPU).  blk receives the
 // workgroup's index within its instance.
-template <int AX>
+template <int AX, int LG = 0>
 __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
     LineCtx lc;
-    lc.lg = g.lg[AX];
+    lc.lg = LG > 0 ? LG : g.lg[AX];  // a compile-time size folds every index below
     lc.M = 1 << lc.lg;
     lc.TPL = lc.M >> 3;
+    lc.wave = AX == 0 && lc.TPL <= 64;  // x lines take consecutive lanes, TPL of them per line
     const int lgC = __ffs(C) - 1;
     const int tid = threadIdx.x;
     if (AX == 0) {
@@ -89,10 +91,19 @@ __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
     return lc;
 }
 
+// The line transform of a pass: the compile-time form for LG > 0, else the run-time one.
+template <typename T, int DIR, int AX, int LG>
+__device__ __forceinline__ void line_fft(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, const LineCtx& lc) {
+    if constexpr (LG > 0)
+        fft_line_ct<T, DIR, LG, AX == 0 && LG <= 9>(v, buf, tw, lc.t);
+    else
+        fft_line<T, DIR>(v, buf, tw, lc.t, lc.lg, lc.wave);
+}
+
 // Dynamic LDS layout of a pass: [twiddles M][lines C * line_stride(M)][reduction scratch].
 template <typename T>
-__host__ __device__ inline size_t pass_lds_bytes(int M, int C, int threads, int K) {
-    size_t b = sizeof(C2<T>) * ((size_t)M + (size_t)C * line_stride(M));
+__host__ __device__ inline size_t pass_lds_bytes(int M, int C, int threads, int K, int axis) {
+    size_t b = sizeof(C2<T>) * ((size_t)M + (size_t)C * line_stride(M, (int)sizeof(C2<T>), axis, C));
     b = (b + 15) & ~(size_t)15;
     b += sizeof(double) * (size_t)((((threads + 63) / 64) + 1) * (K > 0 ? K : 1) + 4);
     return b;
@@ -157,15 +168,19 @@ constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 //                            C2<T>* buf, const C2<T>* tw) const;   (buf/tw: to transform more lines)
 //   __device__ void store(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
 // K sums are accumulated per thread in FP64 and reduced deterministically into pr.parts.
-template <typename T, int AX, class Op, int MAXT, bool EARLY>
+// LG > 0: the kernel is specialised for lines of 2^LG points (g.lg[AX] == LG), so the transform's
+// stages, strides and LDS offsets are compile-time constants; LG = 0 takes the size at run time.
+template <typename T, int AX, class Op, int MAXT, bool EARLY, int LG>
 __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op,
                                                     Partials pr) {
     extern __shared__ double4 smem_raw[];
     int blk_in_inst;
-    LineCtx lc = decode_line<AX>(g, C, blk_in_inst);
+    LineCtx lc = decode_line<AX, LG>(g, C, blk_in_inst);
     C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
-    C2<T>* buf = tw + lc.M + (size_t)lc.c * line_stride(lc.M);
-    size_t off = sizeof(C2<T>) * ((size_t)lc.M + (size_t)C * line_stride(lc.M));
+    constexpr int kPB = (int)sizeof(C2<T>);
+    const int stride_pts = line_stride(lc.M, kPB, AX, C);
+    C2<T>* buf = tw + lc.M + (size_t)lc.c * stride_pts;
+    size_t off = sizeof(C2<T>) * ((size_t)lc.M + (size_t)C * stride_pts);
     off = (off + 15) & ~(size_t)15;
     double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem_raw) + off);
     lc.sc = nullptr;
@@ -220,9 +235,9 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
     for (int k = 0; k < (Op::K > 0 ? Op::K : 1); ++k) acc[k] = ((Op::MAXMASK >> k) & 1u) ? 0.0 : 0.0;
 
     op.load(g, lc, st, v, acc);
-    if (Op::FWD) fft_line<T, -1>(v, buf, tw, lc.t, lc.lg);
+    if (Op::FWD) line_fft<T, -1, AX, LG>(v, buf, tw, lc);
     op.spectral(g, lc, st, v, acc, buf, tw);
-    if (Op::INV) fft_line<T, +1>(v, buf, tw, lc.t, lc.lg);
+    if (Op::INV) line_fft<T, +1, AX, LG>(v, buf, tw, lc);
     if constexpr (!EARLY && Op::PREFETCH) op.prefetch_tail(g, lc, st);
     op.store(g, lc, st, v, acc);
 

@@ -477,10 +477,10 @@ struct OpResid {
                              const C2<T>*) const {
         if constexpr (ONE) {
             const Scal& s = *lc.sc;
-            const double invN = 1.0 / lc.M;
+            const double invN = ldexp(1.0, -lc.lg);  // 1/M, exact
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const double k = freq_of(lc.k(q), lc.M, s.L[0]);
+                const double k = freq_of(lc.k(q), lc.M, s.dk[0]);
                 v[q] = scl(v[q], (T)(invN / (s.lamt + 0.5 * k * k)));
             }
         }
@@ -549,17 +549,17 @@ struct OpPMid {
             const Scal& s = *lc.sc;
             double ko;
             if (AX == 1) {
-                const double xi = freq_of(lc.i1, g.n[0], s.L[0]);
+                const double xi = freq_of(lc.i1, g.n[0], s.dk[0]);
                 ko = xi * xi;
             } else {
-                const double xi = freq_of(lc.i1, g.n[0], s.L[0]);
-                const double mu = freq_of(lc.i2, g.n[1], s.L[1]);
+                const double xi = freq_of(lc.i1, g.n[0], s.dk[0]);
+                const double mu = freq_of(lc.i2, g.n[1], s.dk[1]);
                 ko = xi * xi + mu * mu;
             }
-            const double invN = 1.0 / (double)g.N;
+            const double invN = ldexp(1.0, -(g.lg[0] + g.lg[1] + g.lg[2]));  // 1/N, exact
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const double k = freq_of(lc.k(q), lc.M, s.L[AX]);
+                const double k = freq_of(lc.k(q), lc.M, s.dk[AX]);
                 v[q] = scl(v[q], (T)(invN / (s.lamt + 0.5 * (ko + k * k))));
             }
         }
@@ -717,15 +717,15 @@ struct OpLp {
                              C2<T>* buf, const C2<T>* tw) const {
         const Scal& s = *lc.sc;
         const double rot = rot_coef_s<AX>(s, lc);
-        const double invM = 1.0 / lc.M;
+        const double invM = ldexp(1.0, -lc.lg);  // 1/M, exact
         if (AX < 2 && s.omega != 0.0 && s.dim >= 2) {
             C2<T> u[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) u[q] = st.ph[q];
-            fft_line<T, -1>(u, buf, tw, lc.t, lc.lg);
+            fft_line<T, -1>(u, buf, tw, lc.t, lc.lg, lc.wave);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const double xi = freq_of(lc.k(q), lc.M, s.L[AX]);
+                const double xi = freq_of(lc.k(q), lc.M, s.dk[AX]);
                 const double wr = rot * xi * invM;
                 acc[B_CR] += wr * (double)abs2(v[q]);
                 acc[B_AR] += wr * (double)abs2(u[q]);
@@ -734,7 +734,7 @@ struct OpLp {
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const double xi = freq_of(lc.k(q), lc.M, s.L[AX]);
+            const double xi = freq_of(lc.k(q), lc.M, s.dk[AX]);
             v[q] = scl(v[q], (T)((0.5 * xi * xi + rot * xi) * invM));
         }
     }

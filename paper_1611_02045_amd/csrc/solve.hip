@@ -229,6 +229,7 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
         for (int a = 0; a < 3; ++a) {
             gb.L[a] = host_S[b].L[a];
             gb.h[a] = host_S[b].h[a];
+            gb.dk[a] = host_S[b].dk[a];
         }
         gb.cell = host_S[b].cell;
         if ((e = refresh_instance<T>(gb, *pa.tw, f, (int64_t)b * N, S_dir + b, host_S[b].beta, host_S[b].omega,
@@ -274,6 +275,8 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
                 for (int a = 0; a < 3; ++a) {
                     gb.L[a] = host_S[b].L[a];
                     gb.h[a] = host_S[b].h[a];
+                    gb.dk[a] = host_S[b].dk[a];
+            gb.dk[a] = host_S[b].dk[a];
                 }
                 gb.cell = host_S[b].cell;
                 if ((e = refresh_instance<T>(gb, *pa.tw, c.f, (int64_t)b * N, S_dir + b, host_S[b].beta,
@@ -391,6 +394,7 @@ Scal make_scal(const gpe_problem_t& p, const Geo& g, const gpe_pcg_opts_t& o) {
     s.dim = p.dim;
     for (int a = 0; a < 3; ++a) {
         s.L[a] = g.L[a];
+        s.dk[a] = g.dk[a];
         s.h[a] = g.h[a];
     }
     s.tol_res = o.tol_res_inf;
