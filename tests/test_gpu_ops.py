@@ -15,6 +15,7 @@ SHAPES = [
     (1, (8,), (2.0,)),
     (1, (256,), (16.0,)),
     (1, (1024,), (20.0,)),
+    (1, (512,), (16.0,)),
     (2, (8, 8), (3.0, 3.0)),
     (2, (16, 64), (4.0, 6.0)),
     (2, (64, 16), (6.0, 4.0)),
@@ -22,6 +23,8 @@ SHAPES = [
     (2, (1024, 8), (12.0, 2.0)),
     (2, (256, 256), (16.0, 16.0)),
     (2, (512, 512), (16.0, 16.0)),
+    (2, (512, 32), (16.0, 6.0)),
+    (2, (32, 512), (6.0, 16.0)),
     (3, (8, 8, 8), (3.0, 3.0, 3.0)),
     (3, (16, 32, 8), (4.0, 5.0, 3.0)),
     (3, (64, 64, 64), (8.0, 8.0, 8.0)),
@@ -88,8 +91,13 @@ def test_energy_matches_oracle(torch_gpu, dim, n, L, dtype):
         assert abs(parts[key] - val) < TOL[dtype] * scale, key
 
 
+PRECOND_SHAPES = {"1d": (1, (256,), (16.0,)), "2d-aniso": (2, (16, 64), (4.0, 6.0)), "2d": (2, (256, 256), (16.0, 16.0)),
+                  "2d-512x": (2, (512, 32), (16.0, 6.0)), "2d-512y": (2, (32, 512), (6.0, 16.0)),
+                  "3d": (3, (16, 32, 8), (4.0, 5.0, 3.0))}
+
+
 @pytest.mark.parametrize("kind", ["none", "kinetic", "potential", "combined", "c1", "c2"])
-@pytest.mark.parametrize("dim,n,L", [SHAPES[1], SHAPES[4], SHAPES[8], SHAPES[11]], ids=["1d", "2d-aniso", "2d", "3d"])
+@pytest.mark.parametrize("dim,n,L", list(PRECOND_SHAPES.values()), ids=list(PRECOND_SHAPES))
 def test_preconditioners_match_oracle(torch_gpu, dim, n, L, kind):
     from paper_1611_02045_amd import gpe
     torch = torch_gpu

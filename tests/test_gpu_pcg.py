@@ -189,3 +189,29 @@ def test_3d_rotating_workload_mixed(torch_gpu):
     assert float(np.max(np.abs(r))) <= 1.2e-8
     assert abs(O.energy(prob, V, phi) - rep["E"]) < 1e-10 * abs(rep["E"])
     assert abs(lam - rep["lam"]) < 1e-10 * abs(lam)
+
+
+def test_trajectory_512_lines_single_and_batched(torch_gpu):
+    """512^2 (lines of 512 points: the compile-time transform): the first iterations of a single
+    solve (few workgroups: fields fetched early) and of three instances solved together (many
+    workgroups: fields fetched late) agree with the oracle."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob = Problem(2, (512, 512), (16.0, 16.0), 1000.0, 0.9)
+    V = harmonic_potential(prob)
+    starts = [vortex_seed_2d(prob, s) for s in (103, 107, 109)]
+    iters = 6
+    print("trajectory 512^2", flush=True)
+    refs = [O.pcg(prob, V, p0, tol_res=1e-30, max_iter=iters, record=True) for p0 in starts]
+    rep, _, hist = _gpu_solve(torch, prob, V, starts[0], tol_res=1e-30, max_iter=iters, record_history=1,
+                              check_every=2)
+    assert rep["iters"] == iters
+    for h_ref, h in zip(refs[0].history, hist):
+        assert abs(h["E"] - h_ref["E"]) < 1e-11 * abs(h_ref["E"])
+        assert abs(h["res"] - h_ref["res"]) < 1e-8 * h_ref["res"]
+    Vd = _dev(torch, V)
+    phis = [_dev(torch, p0) for p0 in starts]
+    _, reps = gpe.pcg_solve_batched([prob] * 3, [Vd] * 3, phis, "f64", tol=1e-30, max_iter=iters)
+    for r, ref in zip(reps, refs):
+        assert r["status"] == 1 and r["iters"] == iters
+        assert abs(r["E"] - ref.E) < 1e-11 * abs(ref.E)
