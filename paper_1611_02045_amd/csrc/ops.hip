@@ -41,6 +41,7 @@ struct OpApply {
 #pragma unroll
         for (int s = 0; s < 8; ++s) st.f0[s] = v[s] = f[lc.at(s)];
     }
+    template <int LG>
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
                              const C2<T>*) const {
         const double rot = rot_coef<AX>(g, lc, omega);
@@ -132,6 +133,7 @@ struct OpEnergy {
 #pragma unroll
         for (int s = 0; s < 8; ++s) st.f0[s] = v[s] = phi[lc.at(s)];
     }
+    template <int LG>
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[4], C2<T>*,
                              const C2<T>*) const {
         const double rot = rot_coef<AX>(g, lc, omega);
@@ -253,6 +255,7 @@ struct OpPre {
             if (pre) v[s] = scl(v[s], pv_scale<T>(pre, a, V[i], abs2(phi[i]), beta));
         }
     }
+    template <int LG>
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
                              const C2<T>*) const {
         if (!(F && I)) return;

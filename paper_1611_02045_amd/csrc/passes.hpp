@@ -197,15 +197,19 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
     // (four named registers rather than an array, which the compiler may demote to scratch)
     auto tw_at = [&](int j) { return min((int)(threadIdx.x + j * blockDim.x), lc.M - 1); };
     C2<T> tw0, tw1, tw2, tw3;
-    if constexpr (EARLY) {
+    // A fixed-size transform in a launch too small to fill the chip reads its few twiddles per
+    // stage straight from the global table (cached), sparing the table's copy into LDS; otherwise
+    // the table is staged in LDS, whose latency the transform's dependent reads need.
+    constexpr bool kTwGlobal = LG > 0 && EARLY;
+    if constexpr (EARLY && !kTwGlobal) {
         tw0 = twg[tw_at(0)];
         tw1 = twg[tw_at(1)];
         tw2 = twg[tw_at(2)];
         tw3 = twg[tw_at(3)];
-        if constexpr (Op::PREFETCH) {
-            op.prefetch(g, lc, st);
-            op.prefetch_tail(g, lc, st);
-        }
+    }
+    if constexpr (EARLY && Op::PREFETCH) {
+        op.prefetch(g, lc, st);
+        op.prefetch_tail(g, lc, st);
     }
     if constexpr (Op::SCALARS) {
         __shared__ Scal s_local;
@@ -213,7 +217,7 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
         if (s_local.done) return;                       // uniform per block (one instance per block)
         lc.sc = &s_local;
     }
-    if constexpr (EARLY) {
+    if constexpr (EARLY && !kTwGlobal) {
         auto tw_put = [&](int j, C2<T> x) {
             const int i = threadIdx.x + j * blockDim.x;
             if (i < lc.M) tw[i] = x;
@@ -223,21 +227,22 @@ __global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* _
         tw_put(2, tw2);
         tw_put(3, tw3);
         for (int i = threadIdx.x + kTwiddleRegs * blockDim.x; i < lc.M; i += blockDim.x) tw[i] = twg[i];
-    } else {
+    } else if constexpr (!EARLY) {
         for (int i = threadIdx.x; i < lc.M; i += blockDim.x) tw[i] = twg[i];
         if constexpr (Op::PREFETCH) op.prefetch(g, lc, st);
     }
-    __syncthreads();
+    if constexpr (!kTwGlobal) __syncthreads();  // the LDS twiddle table is complete
 
     C2<T> v[8];
     double acc[Op::K > 0 ? Op::K : 1];
 #pragma unroll
     for (int k = 0; k < (Op::K > 0 ? Op::K : 1); ++k) acc[k] = ((Op::MAXMASK >> k) & 1u) ? 0.0 : 0.0;
 
+    const C2<T>* twx = kTwGlobal ? twg : tw;
     op.load(g, lc, st, v, acc);
-    if (Op::FWD) line_fft<T, -1, AX, LG>(v, buf, tw, lc);
-    op.spectral(g, lc, st, v, acc, buf, tw);
-    if (Op::INV) line_fft<T, +1, AX, LG>(v, buf, tw, lc);
+    if (Op::FWD) line_fft<T, -1, AX, LG>(v, buf, twx, lc);
+    op.template spectral<LG>(g, lc, st, v, acc, buf, twx);
+    if (Op::INV) line_fft<T, +1, AX, LG>(v, buf, twx, lc);
     if constexpr (!EARLY && Op::PREFETCH) op.prefetch_tail(g, lc, st);
     op.store(g, lc, st, v, acc);
 

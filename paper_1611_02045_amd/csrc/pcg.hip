@@ -473,6 +473,7 @@ struct OpResid {
             }
         }
     }
+    template <int LG>
     __device__ void spectral(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[K], C2<T>*,
                              const C2<T>*) const {
         if constexpr (ONE) {
@@ -543,6 +544,7 @@ struct OpPMid {
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = st.w[q];
     }
+    template <int LG>
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
                              const C2<T>*) const {
         if constexpr (F && I) {
@@ -608,6 +610,7 @@ struct OpPLast {
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = st.w[q];
     }
+    template <int LG>
     __device__ void spectral(const Geo&, const LineCtx&, State&, C2<T> (&)[8], double (&)[K], C2<T>*,
                              const C2<T>*) const {}
     __device__ void store(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K]) const {
@@ -713,6 +716,7 @@ struct OpLp {
             st.p[q] = v[q] = scl(p, inv);
         }
     }
+    template <int LG>
     __device__ void spectral(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K],
                              C2<T>* buf, const C2<T>* tw) const {
         const Scal& s = *lc.sc;
@@ -722,7 +726,7 @@ struct OpLp {
             C2<T> u[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) u[q] = st.ph[q];
-            fft_line<T, -1>(u, buf, tw, lc.t, lc.lg, lc.wave);
+            line_fft<T, -1, AX, LG>(u, buf, tw, lc);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const double xi = freq_of(lc.k(q), lc.M, s.dk[AX]);
