@@ -26,7 +26,7 @@ __device__ __forceinline__ double rot_coef(const Geo& g, const LineCtx& lc, doub
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX>
 struct OpApply {
-    static constexpr bool FWD = true, INV = true, SCALARS = false, PREFETCH = false;
+    static constexpr bool FWD = true, INV = true, SCALARS = false, PREFETCH = false, WIDE = false;
     static constexpr int K = 0;
     static constexpr unsigned MAXMASK = 0;
     const C2<T>* f;
@@ -122,7 +122,7 @@ hipError_t op_apply(const Geo& g, bool f64, int B, const Twiddles& tw, const voi
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX>
 struct OpEnergy {
-    static constexpr bool FWD = true, INV = false, SCALARS = false, PREFETCH = false;
+    static constexpr bool FWD = true, INV = false, SCALARS = false, PREFETCH = false, WIDE = false;
     static constexpr int K = 4;
     static constexpr unsigned MAXMASK = 0;
     const C2<T>* phi;
@@ -235,7 +235,7 @@ __device__ __forceinline__ T pv_scale(int kind, double alpha, T V, T rho, double
 
 template <typename T, int AX, bool F, bool I>
 struct OpPre {
-    static constexpr bool FWD = F, INV = I, SCALARS = false, PREFETCH = false;
+    static constexpr bool FWD = F, INV = I, SCALARS = false, PREFETCH = false, WIDE = false;
     static constexpr int K = 0;
     static constexpr unsigned MAXMASK = 0;
     const C2<T>* in;

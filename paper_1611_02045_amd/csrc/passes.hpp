@@ -157,6 +157,7 @@ constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 //   static constexpr bool FWD, INV;  static constexpr int K;  static constexpr unsigned MAXMASK;
 //   static constexpr bool SCALARS;   (bit k of MAXMASK set: sum k is a max-reduction)
 //   static constexpr bool PREFETCH;
+//   static constexpr bool WIDE;      (register-heavy: no occupancy target, see below)
 //   struct State;
 //   __device__ void prefetch(const Geo&, const LineCtx&, State&) const;       // if PREFETCH: load()'s inputs
 //   __device__ void prefetch_tail(const Geo&, const LineCtx&, State&) const;  // if PREFETCH: store()'s inputs
@@ -168,11 +169,15 @@ constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 //                            C2<T>* buf, const C2<T>* tw) const;   (buf/tw: to transform more lines)
 //   __device__ void store(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
 // K sums are accumulated per thread in FP64 and reduced deterministically into pr.parts.
+// Launches with several workgroups per CU (!EARLY) ask the register allocator for the occupancy
+// the LDS footprint allows: four 4-wave workgroups per CU for 8-byte points, three for 16-byte
+// points (their line buffers take about 45 KB of the 160 KB).  A WIDE Op keeps more live state than
+// that budget and would spill, so it is left unconstrained.
 // LG > 0: the kernel is specialised for lines of 2^LG points (g.lg[AX] == LG), so the transform's
 // stages, strides and LDS offsets are compile-time constants; LG = 0 takes the size at run time.
 template <typename T, int AX, class Op, int MAXT, bool EARLY, int LG>
-__global__ __launch_bounds__(MAXT) void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op,
-                                                    Partials pr) {
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(EARLY || Op::WIDE ? 1 : (sizeof(T) == 4 ? 4 : 3))))
+void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op, Partials pr) {
     extern __shared__ double4 smem_raw[];
     int blk_in_inst;
     LineCtx lc = decode_line<AX, LG>(g, C, blk_in_inst);

@@ -419,7 +419,7 @@ using IntakeA = IntakeAbsorb<A_K, kARowsPerThread>;
 // ---------------------------------------------------------------------------------------------
 template <typename T, bool ONE>
 struct OpResid {
-    static constexpr bool FWD = true, INV = ONE, SCALARS = true, PREFETCH = true;
+    static constexpr bool FWD = true, INV = ONE, SCALARS = true, PREFETCH = true, WIDE = true;
     static constexpr int K = A_K;
     static constexpr unsigned MAXMASK = A_MAXMASK;
     IterFields<T> f;
@@ -509,7 +509,7 @@ struct OpResid {
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX, bool F, bool I, bool ABS>
 struct OpPMid {
-    static constexpr bool FWD = F, INV = I, SCALARS = true, PREFETCH = true;
+    static constexpr bool FWD = F, INV = I, SCALARS = true, PREFETCH = true, WIDE = false;
     static constexpr int K = 0;
     static constexpr unsigned MAXMASK = 0;
     C2<T>* w;
@@ -577,7 +577,7 @@ struct OpPMid {
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 struct OpPLast {
-    static constexpr bool FWD = false, INV = true, SCALARS = true, PREFETCH = true;
+    static constexpr bool FWD = false, INV = true, SCALARS = true, PREFETCH = true, WIDE = sizeof(T) == 8;
     static constexpr int K = A_K;
     static constexpr unsigned MAXMASK = A_MAXMASK;
     IterFields<T> f;
@@ -636,7 +636,7 @@ struct OpPLast {
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX, bool FIRST, bool LAST>
 struct OpLp {
-    static constexpr bool FWD = true, INV = true, SCALARS = true, PREFETCH = true;
+    static constexpr bool FWD = true, INV = true, SCALARS = true, PREFETCH = true, WIDE = true;
     static constexpr bool PHI = FIRST || LAST || AX < 2;  // phi is read (x, y: for the rotation sums when omega != 0)
     static constexpr int K = B_K;
     static constexpr unsigned MAXMASK = B_MAXMASK;
