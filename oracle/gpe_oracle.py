@@ -407,6 +407,67 @@ def pcg(prob, V, phi0, *, method: str = "pcg", precond: str = "combined", tol_re
 
 
 # ----------------------------------------------------------------------------------------------
+# Nested grids (Section 6, the multigrid preparation of initial data)
+# ----------------------------------------------------------------------------------------------
+
+def refined(prob):
+    """The same box with twice the points per axis (level p -> p + 1 of the nested grids)."""
+    import dataclasses
+    n = tuple(2 * int(prob.n[a]) if a < prob.dim else int(prob.n[a]) for a in range(len(prob.n)))
+    return dataclasses.replace(prob, n=n)
+
+
+def prolong(prob, f) -> np.ndarray:
+    """Interpolate a grid function of `prob` onto the grid with twice the points per axis and the
+    same box, axis by axis, by its trigonometric interpolant (the interpolation step of the nested
+    grids of Section 6; reading: the paper does not name the interpolation, and the spectral one
+    matches its Fourier discretisation).  Along an axis of M points the coefficients X_p,
+    -M/2 < p < M/2, are kept; the Nyquist coefficient X_{-M/2} is split evenly between the
+    frequencies -M/2 and +M/2 of the fine grid (reading: the symmetric split keeps real data real
+    and is the interpolant of least norm); the fine grid's other coefficients are zero.  Coarse
+    points are fine points 0, 2, 4, ...; there the result equals the input."""
+    out = np.asarray(f, dtype=np.complex128)
+    for a in range(prob.dim):
+        ax = prob.dim - 1 - a
+        M = out.shape[ax]
+        X = np.fft.fft(out, axis=ax)
+        shape = list(out.shape)
+        shape[ax] = 2 * M
+        Y = np.zeros(shape, dtype=np.complex128)
+
+        def put(dst, src, scale):
+            sl_d = [slice(None)] * out.ndim
+            sl_s = [slice(None)] * out.ndim
+            sl_d[ax], sl_s[ax] = dst, src
+            Y[tuple(sl_d)] += scale * X[tuple(sl_s)]
+
+        # fine inverse transform carries 1/(2M): coefficients double to evaluate the same sum
+        put(slice(0, M // 2), slice(0, M // 2), 2.0)                      # p = 0 .. M/2 - 1
+        put(slice(2 * M - M // 2 + 1, 2 * M), slice(M // 2 + 1, M), 2.0)  # p = -M/2 + 1 .. -1
+        put(slice(M // 2, M // 2 + 1), slice(M // 2, M // 2 + 1), 1.0)    # Nyquist, at +M/2 ...
+        put(slice(2 * M - M // 2, 2 * M - M // 2 + 1), slice(M // 2, M // 2 + 1), 1.0)  # ... and -M/2
+        out = np.fft.ifft(Y, axis=ax)
+    return out
+
+
+def pcg_nested(probs, Vs, phi0, *, tol_coarse: float = 1e-6, tol_res: float = 1e-8, max_iter: int = 20_000,
+               **kw):
+    """Ground state on nested grids (Section 6): solve on the coarsest grid from phi0, interpolate
+    the converged state onto the next grid (prolong), renormalise it and solve again, up to the
+    finest grid.  probs[l], Vs[l]: the problem and potential of level l (each grid twice the
+    previous one per axis, same box); the coarse levels stop at ||r||_inf <= tol_coarse, the finest
+    at tol_res.  Returns the finest level's SolveResult and the list of all levels' results."""
+    results = []
+    phi = phi0
+    for lvl, (prob, V) in enumerate(zip(probs, Vs)):
+        if lvl > 0:
+            phi = prolong(probs[lvl - 1], results[-1].phi)
+        last = lvl == len(probs) - 1
+        results.append(pcg(prob, V, phi, tol_res=tol_res if last else tol_coarse, max_iter=max_iter, **kw))
+    return results[-1], results
+
+
+# ----------------------------------------------------------------------------------------------
 # Backward Euler imaginary-time scheme (Section 4), used as an independent check of PCG
 # ----------------------------------------------------------------------------------------------
 
