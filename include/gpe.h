@@ -98,6 +98,16 @@ int gpe_apply_H_batched(gpe_plan_t* plan, int count, const void* phi, const void
 int gpe_precond(gpe_plan_t* plan, int kind, const void* phi, const void* V, double alpha,
                 const void* r, void* Pr, void* stream);
 
+/* Interpolation onto the grid with twice the points per axis and the same box: the step between
+ * the nested grids M_p -> M_{p+1} of the initial-data example of Section 6.2.  Per axis, the
+ * trigonometric interpolant of the Section 3 discretisation, with the Nyquist coefficient split
+ * evenly between the frequencies -M/2 and +M/2 (values at the plan's grid points are kept, real
+ * fields stay real).  in: device field on the plan's grid, of the plan's dtype; out: device field
+ * of 2^dim N points, shape (2 n_z, 2 n_y, 2 n_x), same dtype, not aliasing in.  The norm is not
+ * restored (the solver normalises its start).  GPE_EUNSUPPORTED when 2n exceeds 1024 on an axis.
+ * Uses the plan's scratch (2N or 4N complex values in 2-D / 3-D).  Asynchronous. */
+int gpe_prolong(gpe_plan_t* plan, const void* in, void* out, void* stream);
+
 /* Solver options. */
 typedef struct gpe_pcg_opts {
     int32_t method;        /* 0 = projected preconditioned gradient (Algorithm 1), 1 = PCG (Algorithm 2) */
@@ -151,6 +161,22 @@ int gpe_pcg_history(gpe_plan_t* plan, double* hist, int cap);
 int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void* const* V,
                           void* const* phi_inout, const gpe_pcg_opts_t* opts,
                           gpe_pcg_report_t* reports, void* stream);
+
+/* Ground states on nested grids (the multigrid preparation of initial data, Section 6.2): the
+ * `count` instances are solved together (as gpe_pcg_solve_batched) on the coarsest grid from
+ * phi_coarse, each converged state is interpolated (gpe_prolong) onto the grid with twice the
+ * points per axis and solved again, for `levels` grids in all.  coarsest[i]: the problem of
+ * instance i on the coarsest grid (level l has n << l points per axis, same box, beta, omega).
+ * V: levels * count device potentials, level-major (V[l * count + i] on the level-l grid).
+ * phi_coarse[i]: device start on the coarsest grid (read only).  phi_fine[i]: device output on
+ * the finest grid.  opts: every level; the coarse levels stop at ||r||_inf <= tol_coarse instead
+ * of opts->tol_res_inf.  reports: host, levels * count, level-major.  dtype as in
+ * gpe_pcg_solve_batched.  Returns the worst status of the finest level (a coarse level that does
+ * not converge still hands on its state), or the first error.  Synchronises. */
+int gpe_pcg_solve_nested(int count, int levels, const gpe_problem_t* coarsest, int dtype,
+                         void* const* V, void* const* phi_coarse, void* const* phi_fine,
+                         const gpe_pcg_opts_t* opts, double tol_coarse,
+                         gpe_pcg_report_t* reports, void* stream);
 
 /* Backward of the energy (conjugate-Wirtinger convention of real-valued losses):
  * grad_phi = 2 h^d H_phi phi (device, complex), grad_V = h^d |phi|^2 (device, real, nullable),

@@ -232,6 +232,19 @@ int gpe_precond(gpe_plan_t* plan, int kind, const void* phi, const void* V, doub
     return GPE_OK;
 }
 
+int gpe_prolong(gpe_plan_t* plan, const void* in, void* out, void* stream) {
+    NEEDPTR(plan, "plan");
+    NEEDPTR(in, "in");
+    NEEDPTR(out, "out");
+    if (in == out) { set_error("out must not alias in"); return GPE_EINVAL; }
+    for (int a = 0; a < plan->g.dim; ++a)
+        if (2 * plan->g.n[a] > 1024) { set_error("the refined grid exceeds 1024 points per axis"); return GPE_EUNSUPPORTED; }
+    const size_t cb = plan->f64() ? 16 : 8;
+    if (plan->g.dim > 1) HIPCHK(plan->tmp.ensure(cb * (size_t)plan->g.N * (plan->g.dim == 2 ? 2 : 4)));
+    HIPCHK(op_prolong(plan->g, plan->f64(), plan->tw, in, out, plan->tmp.ptr, (hipStream_t)stream));
+    return GPE_OK;
+}
+
 int gpe_energy_grad(gpe_plan_t* plan, const void* phi, const void* V, void* grad_phi, void* grad_V, double* dE_dbeta,
                     double* dE_domega, void* stream) {
     NEEDPTR(plan, "plan");

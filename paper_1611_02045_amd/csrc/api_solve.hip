@@ -440,4 +440,78 @@ int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void
     return worst;
 }
 
+int gpe_pcg_solve_nested(int count, int levels, const gpe_problem_t* coarsest, int dtype, void* const* V,
+                         void* const* phi_coarse, void* const* phi_fine, const gpe_pcg_opts_t* opts, double tol_coarse,
+                         gpe_pcg_report_t* reports, void* stream) {
+    if (count < 1 || levels < 1 || !coarsest || !V || !phi_coarse || !phi_fine || !reports) {
+        set_error("invalid nested-solve arguments");
+        return GPE_EINVAL;
+    }
+    if (dtype != GPE_F64 && dtype != GPE_F32) { set_error("dtype must be GPE_F64 or GPE_F32"); return GPE_EINVAL; }
+    if (!(tol_coarse > 0.0) || !std::isfinite(tol_coarse)) { set_error("tol_coarse must be positive"); return GPE_EINVAL; }
+    int st = validate_opts(opts);
+    if (st != GPE_OK) return st;
+    // level l: the coarsest problem with 2^l times the points per axis, same box
+    std::vector<std::vector<gpe_problem_t>> probs(levels, std::vector<gpe_problem_t>(coarsest, coarsest + count));
+    for (int l = 0; l < levels; ++l)
+        for (int i = 0; i < count; ++i) {
+            for (int a = 0; a < probs[l][i].dim; ++a) probs[l][i].n[a] = coarsest[i].n[a] << l;
+            if ((st = validate_problem(&probs[l][i])) != GPE_OK) return st;
+            if (!V[(size_t)l * count + i]) { set_error("NULL potential in nested solve"); return GPE_EINVAL; }
+        }
+    for (int i = 0; i < count; ++i)
+        if (!phi_coarse[i] || !phi_fine[i]) { set_error("NULL field in nested solve"); return GPE_EINVAL; }
+    struct Owned {  // device memory of the call, released on every return path
+        std::vector<DevBuf> bufs;
+        Twiddles tw;
+        ~Owned() {
+            for (DevBuf& b : bufs) b.release();
+            for (int a = 0; a < 3; ++a) {
+                tw.t64[a].release();
+                tw.t32[a].release();
+            }
+        }
+    } own;
+    own.bufs.resize((size_t)levels + 1);  // one field set per coarse level, plus interpolation scratch
+    hipStream_t s = (hipStream_t)stream;
+    const size_t cb = dtype == GPE_F64 ? 16 : 8;
+    std::vector<std::vector<void*>> phis(levels, std::vector<void*>(count));
+    for (int l = 0; l < levels; ++l)
+        for (int i = 0; i < count; ++i) {
+            if (l == levels - 1) {
+                phis[l][i] = phi_fine[i];
+                continue;
+            }
+            size_t off = 0, total = 0;
+            for (int j = 0; j < count; ++j) total += cb * (size_t)make_geo(probs[l][j]).N;
+            HIPCHK(own.bufs[l].ensure(total));
+            for (int j = 0; j < i; ++j) off += cb * (size_t)make_geo(probs[l][j]).N;
+            phis[l][i] = (char*)own.bufs[l].ptr + off;
+        }
+    for (int i = 0; i < count; ++i)
+        HIPCHK(hipMemcpyAsync(phis[0][i], phi_coarse[i], cb * (size_t)make_geo(probs[0][i]).N, hipMemcpyDeviceToDevice, s));
+    int worst = GPE_OK;
+    for (int l = 0; l < levels; ++l) {
+        gpe_pcg_opts_t o = *opts;
+        if (l < levels - 1) o.tol_res_inf = tol_coarse;
+        std::vector<void*> Vl(V + (size_t)l * count, V + (size_t)(l + 1) * count);
+        st = gpe_pcg_solve_batched(count, probs[l].data(), dtype, Vl.data(), phis[l].data(), &o,
+                                   reports + (size_t)l * count, stream);
+        if (st < 0 && st != GPE_ELINESEARCH) return st;
+        if (l == levels - 1) {
+            worst = st;
+            break;
+        }
+        // interpolate every instance onto the next grid (the solver renormalises its start)
+        for (int i = 0; i < count; ++i) {
+            const Geo g = make_geo(probs[l][i]);
+            HIPCHK(build_twiddles(g, own.tw));
+            if (g.dim > 1) HIPCHK(own.bufs[levels].ensure(cb * (size_t)g.N * (g.dim == 2 ? 2 : 4)));
+            HIPCHK(op_prolong(g, dtype == GPE_F64, own.tw, phis[l][i], phis[l + 1][i], own.bufs[levels].ptr, s));
+            HIPCHK(hipStreamSynchronize(s));  // the tables are rebuilt for the next instance
+        }
+    }
+    return worst;
+}
+
 }  // extern "C"

@@ -61,6 +61,9 @@ hipError_t op_apply(const Geo& g, bool f64, int B, const Twiddles& tw, const voi
 
 // out = -L_z f (dim >= 2), tmp: one field of workspace.
 hipError_t op_rotation(const Geo& g, bool f64, const Twiddles& tw, const void* f, void* out, void* tmp, hipStream_t s);
+// Interpolation of one field on the grid g onto the grid with twice the points per axis (out:
+// 2^dim N points).  tmp: at least 2N (2-D) or 4N (3-D) complex values; unused in 1-D.
+hipError_t op_prolong(const Geo& g, bool f64, const Twiddles& tw, const void* in, void* out, void* tmp, hipStream_t s);
 
 // Energy parts of one field: dst (device, 4 doubles) <- {kinetic, potential, interaction, rotation}.
 hipError_t op_energy(const Geo& g, bool f64, const Twiddles& tw, const void* phi, const void* V,

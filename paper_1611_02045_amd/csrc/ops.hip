@@ -117,6 +117,97 @@ hipError_t op_apply(const Geo& g, bool f64, int B, const Twiddles& tw, const voi
 }
 
 // ---------------------------------------------------------------------------------------------
+// Interpolation onto the grid with twice the points per axis and the same box (the nested grids
+// of Section 6), one axis per pass, by the trigonometric interpolant of the discretisation with
+// the Nyquist coefficient split evenly between the frequencies -M/2 and +M/2.  At the coarse
+// points the interpolant is the input itself; at the midpoints x_j + h/2 it is the input shifted
+// by half a cell, F^{-1}[e^{i pi p / M} F f] over -M/2 < p < M/2, the split Nyquist pair adding
+// cos(pi/2) = 0 there.  The pass writes both: out[2j] = f[j], out[2j + 1] = the shifted value.
+// The pass geometry is the source's (axes before AX already doubled); out has twice its points.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int AX>
+struct OpProlong {
+    static constexpr bool FWD = true, INV = true, SCALARS = false, PREFETCH = false, WIDE = false;
+    static constexpr int K = 0;
+    static constexpr unsigned MAXMASK = 0;
+    const C2<T>* f;
+    C2<T>* out;
+    struct State { C2<T> f0[8]; };
+    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&)[1]) const {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) st.f0[s] = v[s] = f[lc.at(s)];
+    }
+    template <int LG>
+    __device__ void spectral(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
+                             const C2<T>*) const {
+        const double inv = ldexp(1.0, -lc.lg);  // 1/M, exact
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int j = lc.k(s);
+            const int p = j < (lc.M >> 1) ? j : j - lc.M;
+            if (2 * p == -lc.M) {
+                v[s] = C2<T>{(T)0, (T)0};
+            } else {
+                double sn, cs;
+                sincospi((double)p * inv, &sn, &cs);
+                v[s] = mul(v[s], C2<T>{(T)(cs * inv), (T)(sn * inv)});
+            }
+        }
+    }
+    __device__ void store(const Geo& g, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&)[1]) const {
+        // source offset s (within its instance) -> even output offset: x: 2s; y: 2s - x;
+        // z: 2s - (y n_x + x); the odd neighbour is one output step further along AX.
+        const int64_t nx = g.n[0], nxy = (int64_t)g.n[0] * g.n[1];
+        const int64_t keep = AX == 0 ? 0 : (AX == 1 ? (int64_t)lc.i1 : (int64_t)lc.i2 * nx + lc.i1);
+        const int64_t step = AX == 0 ? 1 : (AX == 1 ? nx : nxy);
+        C2<T>* o = out + 2 * lc.off_b;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int64_t e = 2 * (lc.at(s) - lc.off_b) - keep;
+            o[e] = st.f0[s];
+            o[e + step] = v[s];
+        }
+    }
+};
+
+// g with axes [0, upto) doubled (the geometry of the source of the pass along `upto`).
+static Geo doubled_upto(const Geo& g, int upto) {
+    Geo d = g;
+    for (int a = 0; a < upto; ++a) {
+        d.n[a] *= 2;
+        d.lg[a] += 1;
+        d.N *= 2;
+        d.h[a] *= 0.5;
+        d.cell *= 0.5;
+    }
+    return d;
+}
+
+template <typename T>
+static hipError_t prolong_t(const Geo& g, const Twiddles& tw, const void* in, void* out, void* tmp, hipStream_t s) {
+    const bool f64 = sizeof(T) == 8;
+    Partials none{nullptr, 0, 0, 0};
+    hipError_t e;
+    const C2<T>* src = (const C2<T>*)in;
+    C2<T>* dst = (C2<T>*)out;
+    C2<T>* t = (C2<T>*)tmp;
+    if (g.dim == 1) return launch_pass<T, 0>(g, 1, tw.get(0, f64), OpProlong<T, 0>{src, dst}, none, s);
+    // 2-D: x into tmp (2N), y into out.  3-D: x into the last quarter of out, y into tmp (4N),
+    // z into out (the x result is dead by then; passes on one stream run in order).
+    C2<T>* xo = g.dim == 2 ? t : dst + 6 * g.N;
+    if ((e = launch_pass<T, 0>(g, 1, tw.get(0, f64), OpProlong<T, 0>{src, xo}, none, s)) != hipSuccess) return e;
+    const Geo g1 = doubled_upto(g, 1);
+    if (g.dim == 2) return launch_pass<T, 1>(g1, 1, tw.get(1, f64), OpProlong<T, 1>{xo, dst}, none, s);
+    if ((e = launch_pass<T, 1>(g1, 1, tw.get(1, f64), OpProlong<T, 1>{xo, t}, none, s)) != hipSuccess) return e;
+    const Geo g2 = doubled_upto(g, 2);
+    return launch_pass<T, 2>(g2, 1, tw.get(2, f64), OpProlong<T, 2>{t, dst}, none, s);
+}
+
+hipError_t op_prolong(const Geo& g, bool f64, const Twiddles& tw, const void* in, void* out, void* tmp, hipStream_t s) {
+    return f64 ? prolong_t<double>(g, tw, in, out, tmp, s) : prolong_t<float>(g, tw, in, out, tmp, s);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Energy: forward transforms only; Parseval turns <phi, F^{-1} sigma F phi> into
 // (1/M) sum sigma |F phi|^2 per line.  Sums: {kinetic, rotation, potential, quartic}.
 // ---------------------------------------------------------------------------------------------

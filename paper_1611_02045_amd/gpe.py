@@ -67,6 +67,9 @@ SIGNATURES = {
     "gpe_pcg_history": (_I, [_VP, ctypes.POINTER(_D), _I]),
     "gpe_pcg_solve_batched": (_I, [_I, ctypes.POINTER(Problem), _I, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                    ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
+    "gpe_prolong": (_I, [_VP, _VP, _VP, _VP]),
+    "gpe_pcg_solve_nested": (_I, [_I, _I, ctypes.POINTER(Problem), _I, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                  ctypes.POINTER(_VP), ctypes.POINTER(PcgOpts), _D, ctypes.POINTER(PcgReport), _VP]),
     "gpe_energy_grad": (_I, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), _VP]),
     "gpe_adjoint_solve": (_I, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
     "gpe_adjoint_param_grads": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), _VP]),
@@ -215,6 +218,17 @@ class Plan:
                                          _stream(stream)))
         return out
 
+    def prolong(self, phi, out=None, stream=None):
+        """phi interpolated onto the grid with twice the points per axis (same box)."""
+        fine = tuple(2 * m for m in self.shape)
+        if out is None:
+            out = torch.empty(fine, dtype=self.complex_dtype, device=phi.device)
+        if (not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != self.complex_dtype
+                or not out.is_contiguous() or tuple(out.shape) != fine):
+            raise ValueError(f"out must be a contiguous {self.complex_dtype} device tensor of shape {fine}")
+        _check(lib().gpe_prolong(self._h, self._field(phi, "phi"), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
     def precond(self, kind: str, phi, V, r, alpha: float | None = None, out=None, stream=None):
         if out is None:
             out = torch.empty_like(r)
@@ -324,3 +338,39 @@ def pcg_solve_batched(problems, Vs, phis, dtype: str = "f64", stream=None, **opt
                                      _stream(stream))
     _check(st)
     return st, [r.as_dict() for r in reps]
+
+
+def pcg_solve_nested(problems, Vs_per_level, phis, dtype: str = "f64", tol_coarse: float = 1e-6, stream=None,
+                     **opts):
+    """Ground states on nested grids: problems[i] is instance i on the coarsest grid, Vs_per_level[l][i]
+    its potential on level l (n << l points per axis), phis[i] its start on the coarsest grid.
+    Returns (status, finest-level fields, reports[l][i])."""
+    count, levels = len(problems), len(Vs_per_level)
+    P = (Problem * count)(*[make_problem(p.dim, p.n, p.L, p.beta, p.omega) for p in problems])
+    want_c = torch.complex128 if dtype == "f64" else torch.complex64
+    want_r = torch.float64 if dtype == "f64" else torch.float32
+    Vflat = []
+    for lvl, Vl in enumerate(Vs_per_level):
+        if len(Vl) != count:
+            raise ValueError("one potential per instance and level")
+        for V, p in zip(Vl, problems):
+            shape = tuple(reversed([m << lvl for m in tuple(p.n)[:p.dim]]))
+            if not (V.is_cuda and V.is_contiguous() and V.dtype == want_r and tuple(V.shape) == shape):
+                raise ValueError(f"level-{lvl} potential must be a contiguous {want_r} device tensor of shape {shape}")
+            Vflat.append(V)
+    outs = []
+    for phi, p in zip(phis, problems):
+        shape = tuple(reversed(tuple(p.n)[:p.dim]))
+        if not (phi.is_cuda and phi.is_contiguous() and phi.dtype == want_c and tuple(phi.shape) == shape):
+            raise ValueError(f"start must be a contiguous {want_c} device tensor of shape {shape}")
+        fine = tuple(m << (levels - 1) for m in shape)
+        outs.append(torch.empty(fine, dtype=want_c, device=phi.device))
+    vp = (ctypes.c_void_p * len(Vflat))(*[V.data_ptr() for V in Vflat])
+    pin = (ctypes.c_void_p * count)(*[phi.data_ptr() for phi in phis])
+    pout = (ctypes.c_void_p * count)(*[o.data_ptr() for o in outs])
+    o = default_opts(**opts)
+    reps = (PcgReport * (levels * count))()
+    st = lib().gpe_pcg_solve_nested(count, levels, P, F64 if dtype == "f64" else F32, vp, pin, pout,
+                                    ctypes.byref(o), float(tol_coarse), reps, _stream(stream))
+    _check(st)
+    return st, outs, [[reps[lvl * count + i].as_dict() for i in range(count)] for lvl in range(levels)]
