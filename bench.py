@@ -11,7 +11,8 @@ switch).  At Omega = 0.9 the iteration count to 1e-8 depends strongly on the sta
 vortex-lattice modes): a step lasts as long as its slowest start.
 
 Printed (one JSON line on stdout): the mixed FP32/FP64 time-to-1e-8 of a step as `value`, beside the
-FP64 step time, each start solved alone (mixed and FP64), H_phi applies/s, PCG iterations/s, the
+FP64 step time, each start solved alone (mixed and FP64), the same starts on nested grids 64^2 ->
+512^2 (the paper's multigrid preparation of initial data), H_phi applies/s, PCG iterations/s, the
 dominant kernel's roofline figure (kernel-only HIP event timings of the step's configuration, HBM
 traffic from the committed counter summary) and the CPU oracle timed on the host (bounded sample,
 extrapolated).
@@ -124,6 +125,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the one-start-at-a-time solves")
+    ap.add_argument("--no-nested", action="store_true", help="skip the nested-grid solves")
+    ap.add_argument("--tol-coarse", type=float, default=1e-5, help="residual tolerance of the coarse nested grids")
     ap.add_argument("--profile-iters", type=int, default=30)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-kernel profile of the step's iteration and a 512 MiB copy (counter runs)")
@@ -135,7 +138,7 @@ def main():
 
     import torch
 
-    from gpe_inputs import SEEDS_2D_512_SET, workload_2d_set
+    from gpe_inputs import SEEDS_2D_512_SET, harmonic_potential, workload_2d_set
     from paper_1611_02045_amd import gpe
 
     if not torch.cuda.is_available():
@@ -212,6 +215,32 @@ def main():
                            "pcg_iters_per_s": sum(its) / sum(secs)}
             log(f"[bench] single {tag}: {mean(secs):.4f} s/solve, iters {its}")
 
+    # the same eight starts on nested grids 64^2 -> 512^2 (the paper's multigrid preparation of
+    # initial data): each start generated on the coarsest grid, solved there to tol_coarse,
+    # interpolated and solved again on each finer grid, the last to 1e-8
+    nested = None
+    if not args.no_nested:
+        prob_c, _, starts_c_np = workload_2d_set(64)
+        levels = 4
+        lv_probs = [type(prob_c)(2, (64 << l, 64 << l), prob_c.L, prob_c.beta, prob_c.omega) for l in range(levels)]
+        lv_V = [torch.from_numpy(harmonic_potential(p)).to("cuda") for p in lv_probs]
+        starts_c = [torch.from_numpy(x).to("cuda") for x in starts_c_np]
+        nested = {"levels": [64 << l for l in range(levels)], "tol_coarse": args.tol_coarse}
+        for tag, opts in (("mixed", mixed), ("fp64", fp64)):
+            secs = []
+            for _ in range(max(1, args.steps)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, lrep = gpe.pcg_solve_nested([prob_c] * S, [[Vl] * S for Vl in lv_V], starts_c, "f64",
+                                                  tol_coarse=args.tol_coarse, **opts)
+                torch.cuda.synchronize()
+                secs.append(time.perf_counter() - t0)
+            nested[tag] = {"s_per_step": mean(secs), "iters_per_level": [[r["iters"] for r in lv] for lv in lrep],
+                           "E": [r["E"] for r in lrep[-1]], "res_inf": max(r["res_inf"] for r in lrep[-1]),
+                           "status": [r["status"] for r in lrep[-1]]}
+            log(f"[bench] nested {tag}: {mean(secs):.4f} s/step, iterations per level (max) "
+                f"{[max(r['iters'] for r in lv) for lv in lrep]}")
+
     # H_phi applies/s (single field and a batch of 32 fields, FP64 and FP32)
     log("[bench] H applies")
     plan64 = gpe.Plan.from_problem(prob, "f64")
@@ -278,6 +307,7 @@ def main():
         "iters_mixed": {"per_start": it_mixed, "fp32": [r["iters_fp32"] for r in reps_mixed]},
         "iters_fp64": it_fp64,
         "single_start": single,
+        "nested_grids": nested,
         "pcg_iters_per_s_step": {"mixed": max(it_mixed) / mean(t_mixed), "fp64": max(it_fp64) / mean(t_fp64)},
         "h_applies_per_s": {"fp64": ap64, "fp32": ap32, "fp64_batch32": apb64, "fp32_batch32": apb32},
         "h_apply_batch32_hbm_gbs": {

@@ -66,9 +66,12 @@ inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes, int B =
         C = std::min(C, std::max(1, 256 / TPL));
         C = std::min(C, g.n[0]);
     }
-    // keep at least 64 workgroups so that small grids still spread over the chip; larger groups
-    // keep the per-instance partial rows (which every consumer workgroup reduces) few
-    while (C > 1 && lines / C < 64) C >>= 1;
+    // keep at least 64 workgroups so that small grids still spread over the chip, but never less
+    // than one full wave per workgroup: a partial wave leaves lanes idle and takes the slow
+    // partial-row reduction; larger groups keep the per-instance partial rows (which every
+    // consumer workgroup reduces) few
+    const int Cmin = std::max(1, 64 / TPL);
+    while (C > Cmin && lines / C < 64) C >>= 1;
     while (C > 1 && (lpf % C) != 0) C >>= 1;
     // keep the LDS footprint (twiddles + lines + reduction scratch) within budget
     while (C > 1 && pass_lds_bytes_cb(complex_bytes, g.n[AX], C, C * TPL, 32, AX) > kPassLdsBudget) C >>= 1;
