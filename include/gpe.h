@@ -178,6 +178,22 @@ int gpe_pcg_solve_nested(int count, int levels, const gpe_problem_t* coarsest, i
                          const gpe_pcg_opts_t* opts, double tol_coarse,
                          gpe_pcg_report_t* reports, void* stream);
 
+/* Ground state by the backward Euler discretisation of the normalised gradient flow (the BESP
+ * schemes of Section 4; BE_nu of Section 6).  Outer step n: lambda_n = <phi_n, H phi_n>; stop when
+ * ||H phi_n - lambda_n phi_n||_inf <= opts->tol_res_inf or after opts->max_iter steps; otherwise
+ * solve (I/dt + H_{phi_n} - s lambda_n) phit = phi_n / dt with the nonlinearity frozen at phi_n
+ * (s = 1 when lambda_term, else 0) by preconditioned linear CG from phit = phi_n, to
+ * ||residual|| <= inner_tol ||phi_n / dt|| (at most 10000 inner iterations), and set
+ * phi_{n+1} = phit / ||phit||.  opts->precond: the inner preconditioner (GPE_P_NONE, _KINETIC,
+ * _POTENTIAL or _COMBINED, with shift 1/dt); opts->check_every: inner iterations between polls;
+ * the other options are ignored.  phi_inout: device, normalised on entry, overwritten.
+ * inner_iters: host, nullable, the total of inner iterations (the paper's count for BE_nu).
+ * report: host, nullable (iters = outer steps).  GPE_EINVAL when the inner operator is not
+ * positive definite (dt too large).  Synchronises. */
+int gpe_be_solve(gpe_plan_t* plan, const void* V, void* phi_inout, double dt, int lambda_term,
+                 const gpe_pcg_opts_t* opts, double inner_tol, int64_t* inner_iters,
+                 gpe_pcg_report_t* report, void* stream);
+
 /* Backward of the energy (conjugate-Wirtinger convention of real-valued losses):
  * grad_phi = 2 h^d H_phi phi (device, complex), grad_V = h^d |phi|^2 (device, real, nullable),
  * *dE_dbeta = 1/2 h^d sum |phi|^4 and *dE_domega = -Re<phi, L_z phi> (host, nullable).

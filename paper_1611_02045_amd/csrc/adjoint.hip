@@ -18,59 +18,14 @@
 
 #include "internal.hpp"
 #include "plan.hpp"
+#include "linear.hpp"
 
 namespace gpe {
 
-struct AdjS {
-    double lam, beta, cell, nphi2;  // chemical potential, nonlinearity, h^d, ||phi||^2
-    double rz, pq, rr, rr0, a, b;
-    double tol2;
-    int64_t it, max_it;
-    int32_t done, status;
-};
-
-constexpr int kDotBlocks = 256;
-
-// Partial sums (kDotBlocks per request) of up to 4 products Re or Im of conj(a_k) b_k.
-template <typename T>
-struct DotReq {
-    const C2<T>* a[4];
-    const C2<T>* b[4];
-    int imag[4];
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_dots(DotReq<T> q, int nq, int64_t N, double* parts) {
-    __shared__ double red[4 * 4];
-    __shared__ double out[4];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (k < nq) {
-                const C2<T> x = q.a[k][i], y = q.b[k][i];
-                acc[k] += q.imag[k] ? (double)(x.x * y.y - x.y * y.x) : (double)(x.x * y.x + x.y * y.y);
-            }
-        }
-    }
-    block_reduce<4>(acc, red, out, 0u);
-    if (threadIdx.x < 4) parts[blockIdx.x * 4 + threadIdx.x] = out[threadIdx.x];
-}
-
-// dst[k] = scale * sum over blocks (fixed order) of parts[.][k], k < 4.
-__global__ void k_dots_final(const double* parts, int nb, double scale, double* dst) {
-    __shared__ double red[4 * 4];
-    __shared__ double out[4];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-        for (int k = 0; k < 4; ++k) acc[k] += parts[b * 4 + k];
-    block_reduce<4>(acc, red, out, 0u);
-    if (threadIdx.x < 4) dst[threadIdx.x] = scale * out[threadIdx.x];
-}
 
 // f <- f - (c0 phi + c1 i phi) / ||phi||^2 with c = {Re<phi,f>, Re<i phi,f>} (device).
 template <typename T>
-__global__ void k_project(C2<T>* f, const C2<T>* phi, const double* c, const AdjS* S, int64_t N) {
+__global__ void k_project(C2<T>* f, const C2<T>* phi, const double* c, const CgS* S, int64_t N) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const T c0 = (T)(c[0] / S->nphi2), c1 = (T)(c[1] / S->nphi2);
@@ -81,7 +36,7 @@ __global__ void k_project(C2<T>* f, const C2<T>* phi, const double* c, const Adj
 
 // q <- q + beta |phi|^2 p + 2 beta Re(conj(phi) p) phi - lambda p  (q holds L p on entry).
 template <typename T>
-__global__ void k_hessian(C2<T>* q, const C2<T>* p, const C2<T>* phi, const AdjS* S, int64_t N) {
+__global__ void k_hessian(C2<T>* q, const C2<T>* p, const C2<T>* phi, const CgS* S, int64_t N) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const C2<T> ph = phi[i], pv = p[i];
@@ -91,76 +46,17 @@ __global__ void k_hessian(C2<T>* q, const C2<T>* p, const C2<T>* phi, const AdjS
     q[i] = add(add(q[i], scl(pv, w)), scl(ph, re2));
 }
 
-__global__ void k_adj_alpha(AdjS* S, const double* pq) {
-    if (threadIdx.x != 0 || S->done) return;
-    S->pq = pq[0];
-    if (!(S->pq > 0.0)) {
-        S->status = -1;  // not positive definite: not a local minimum
-        S->done = 1;
-        return;
-    }
-    S->a = S->rz / S->pq;
-}
 
-template <typename T>
-__global__ void k_adj_update(C2<T>* x, C2<T>* r, const C2<T>* p, const C2<T>* q, const AdjS* S, int64_t N) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N || S->done) return;
-    const T a = (T)S->a;
-    x[i] = add(x[i], scl(p[i], a));
-    r[i] = sub(r[i], scl(q[i], a));
-}
 
-// dots = {<r, z>, <r, r>}: convergence test on ||r|| / ||r_0||, then the CG coefficient.
-__global__ void k_adj_beta(AdjS* S, const double* dots) {
-    if (threadIdx.x != 0 || S->done) return;
-    S->it += 1;
-    S->rr = dots[1];
-    if (!(dots[0] == dots[0]) || !(dots[1] == dots[1])) {
-        S->status = -4;
-        S->done = 1;
-        return;
-    }
-    if (S->rr <= S->tol2 * S->rr0) {
-        S->status = 0;
-        S->done = 1;
-        return;
-    }
-    if (S->it >= S->max_it) {
-        S->status = 1;
-        S->done = 1;
-        return;
-    }
-    S->b = dots[0] / S->rz;
-    S->rz = dots[0];
-}
 
-template <typename T>
-__global__ void k_adj_dir(C2<T>* p, const C2<T>* z, const AdjS* S, int64_t N) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N || S->done) return;
-    p[i] = add(z[i], scl(p[i], (T)S->b));
-}
 
-__global__ void k_adj_init(AdjS* S, const double* dots, const double* nphi) {
+__global__ void k_adj_init(CgS* S, const double* dots, const double* nphi) {
     if (threadIdx.x != 0) return;
     S->rz = dots[0];
     S->rr0 = dots[1];
     S->rr = dots[1];
     S->nphi2 = nphi[0];
     if (!(S->rr0 > 0.0)) S->done = 1;  // zero right-hand side: mu = 0
-}
-
-template <typename T>
-__global__ void k_copy_c(const C2<T>* a, C2<T>* b, int64_t N) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) b[i] = a[i];
-}
-
-template <typename T>
-__global__ void k_zero_c(C2<T>* a, int64_t N) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) a[i] = mk((T)0, (T)0);
 }
 
 // grad_V = -h^d Re(conj(mu) phi) (the adjoint part of dl/dV_k).
@@ -177,7 +73,6 @@ __global__ void k_cubic(const C2<T>* phi, C2<T>* v, int64_t N) {
     if (i < N) v[i] = scl(phi[i], abs2(phi[i]));
 }
 
-static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <typename T>
 struct AdjCtx {
@@ -186,7 +81,7 @@ struct AdjCtx {
     const C2<T>* phi;
     const T* V;
     double beta, omega;
-    AdjS* S;
+    CgS* S;
     double* parts;  // kDotBlocks * 4
     double* sc;     // device scalars: [0..3] dots, [4..7] projection coefficients, [8] alpha, [9] ||phi||^2
     C2<T>*x, *r, *z, *p, *q, *w;
@@ -196,13 +91,7 @@ struct AdjCtx {
 template <typename T>
 static hipError_t dots(AdjCtx<T>& c, int nq, const C2<T>* a0, const C2<T>* b0, int i0, const C2<T>* a1,
                        const C2<T>* b1, int i1, double* dst) {
-    DotReq<T> q{};
-    q.a[0] = a0; q.b[0] = b0; q.imag[0] = i0;
-    q.a[1] = a1 ? a1 : a0; q.b[1] = b1 ? b1 : b0; q.imag[1] = i1;
-    q.a[2] = a0; q.b[2] = b0; q.a[3] = a0; q.b[3] = b0;
-    hipLaunchKernelGGL(k_dots<T>, dim3(kDotBlocks), dim3(256), 0, c.s, q, nq, c.g->N, c.parts);
-    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, c.s, c.parts, kDotBlocks, c.g->cell, dst);
-    return hipGetLastError();
+    return field_dots<T>(c.g->N, c.g->cell, c.parts, nq, a0, b0, i0, a1, b1, i1, dst, c.s);
 }
 
 // f <- Pi f: remove the components along phi and i phi.
@@ -224,7 +113,7 @@ static hipError_t precondition(AdjCtx<T>& c, const C2<T>* rin, C2<T>* zout) {
 }
 
 template <typename T>
-static hipError_t adjoint_run(AdjCtx<T>& c, const C2<T>* rhs, int check_every, int64_t max_it, AdjS& hostS) {
+static hipError_t adjoint_run(AdjCtx<T>& c, const C2<T>* rhs, int check_every, int64_t max_it, CgS& hostS) {
     const int64_t N = c.g->N;
     hipError_t e;
     // r = Pi rhs, x = 0, z = Pi P Pi r, p = z
@@ -244,14 +133,14 @@ static hipError_t adjoint_run(AdjCtx<T>& c, const C2<T>* rhs, int check_every, i
             hipLaunchKernelGGL(k_hessian<T>, dim3(nblk(N)), dim3(256), 0, c.s, c.q, c.p, c.phi, c.S, N);
             if ((e = project<T>(c, c.q)) != hipSuccess) return e;
             if ((e = dots<T>(c, 1, c.p, c.q, 0, nullptr, nullptr, 0, c.sc)) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_adj_alpha, dim3(1), dim3(64), 0, c.s, c.S, c.sc);
-            hipLaunchKernelGGL(k_adj_update<T>, dim3(nblk(N)), dim3(256), 0, c.s, c.x, c.r, c.p, c.q, c.S, N);
+            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, c.s, c.S, c.sc);
+            hipLaunchKernelGGL(k_cg_update<T>, dim3(nblk(N)), dim3(256), 0, c.s, c.x, c.r, c.p, c.q, c.S, N);
             if ((e = precondition<T>(c, c.r, c.z)) != hipSuccess) return e;
             if ((e = dots<T>(c, 2, c.r, c.z, 0, c.r, c.r, 0, c.sc)) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_adj_beta, dim3(1), dim3(64), 0, c.s, c.S, c.sc);
-            hipLaunchKernelGGL(k_adj_dir<T>, dim3(nblk(N)), dim3(256), 0, c.s, c.p, c.z, c.S, N);
+            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, c.s, c.S, c.sc);
+            hipLaunchKernelGGL(k_cg_dir<T>, dim3(nblk(N)), dim3(256), 0, c.s, c.p, c.z, c.S, N);
         }
-        if ((e = hipMemcpyAsync(&hostS, c.S, sizeof(AdjS), hipMemcpyDeviceToHost, c.s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(&hostS, c.S, sizeof(CgS), hipMemcpyDeviceToHost, c.s)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(c.s)) != hipSuccess) return e;
         if (hostS.done) break;
     }
@@ -278,7 +167,7 @@ static int adjoint_impl(gpe_plan_t* plan, const void* phi_star, const void* V, c
     const Geo& g = plan->g;
     const int64_t N = g.N;
     const size_t cf = sizeof(C2<T>) * (size_t)N;
-    HIPCHK(plan->tmp.ensure(6 * cf + sizeof(AdjS) + 64 * sizeof(double) + kDotBlocks * 4 * sizeof(double) + 256));
+    HIPCHK(plan->tmp.ensure(6 * cf + sizeof(CgS) + 64 * sizeof(double) + kDotBlocks * 4 * sizeof(double) + 256));
     char* base = (char*)plan->tmp.ptr;
     AdjCtx<T> c;
     c.g = &g;
@@ -294,8 +183,8 @@ static int adjoint_impl(gpe_plan_t* plan, const void* phi_star, const void* V, c
     c.q = (C2<T>*)(base + 3 * cf);
     c.w = (C2<T>*)(base + 4 * cf);
     C2<T>* hphi = (C2<T>*)(base + 5 * cf);
-    c.S = (AdjS*)(base + 6 * cf);
-    c.sc = (double*)(base + 6 * cf + sizeof(AdjS));
+    c.S = (CgS*)(base + 6 * cf);
+    c.sc = (double*)(base + 6 * cf + sizeof(CgS));
     c.parts = c.sc + 64;
     c.s = s;
     // lambda and ||phi||^2 (fresh), lambda~ for the preconditioner
@@ -306,7 +195,7 @@ static int adjoint_impl(gpe_plan_t* plan, const void* phi_star, const void* V, c
     double h2[2];
     HIPCHK(hipMemcpyAsync(h2, c.sc + 12, sizeof(h2), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    AdjS hs;
+    CgS hs;
     std::memset(&hs, 0, sizeof(hs));
     hs.lam = h2[0] / h2[1];
     hs.beta = c.beta;
@@ -314,7 +203,7 @@ static int adjoint_impl(gpe_plan_t* plan, const void* phi_star, const void* V, c
     hs.nphi2 = h2[1];
     hs.tol2 = o->tol_res_inf * o->tol_res_inf;
     hs.max_it = o->max_iter;
-    HIPCHK(hipMemcpyAsync(c.S, &hs, sizeof(AdjS), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.S, &hs, sizeof(CgS), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(c.sc + 9, &h2[1], sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(adjoint_run<T>(c, (const C2<T>*)rhs, std::max(1, o->check_every), o->max_iter, hs));
     const auto t1 = std::chrono::steady_clock::now();

@@ -68,6 +68,8 @@ SIGNATURES = {
     "gpe_pcg_solve_batched": (_I, [_I, ctypes.POINTER(Problem), _I, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                    ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
     "gpe_prolong": (_I, [_VP, _VP, _VP, _VP]),
+    "gpe_be_solve": (_I, [_VP, _VP, _VP, _D, _I, ctypes.POINTER(PcgOpts), _D, ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(PcgReport), _VP]),
     "gpe_pcg_solve_nested": (_I, [_I, _I, ctypes.POINTER(Problem), _I, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                   ctypes.POINTER(_VP), ctypes.POINTER(PcgOpts), _D, ctypes.POINTER(PcgReport), _VP]),
     "gpe_energy_grad": (_I, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), _VP]),
@@ -257,6 +259,20 @@ class Plan:
                                  ctypes.byref(rep), _stream(stream))
         _check(st)
         return rep.as_dict()
+
+    def be_solve(self, V, phi, dt: float, lambda_term: bool = True, inner_tol: float = 1e-10, stream=None, **opts):
+        """Backward Euler ground-state iteration (phi updated in place); the report carries
+        `inner_iters`, the total of inner CG iterations."""
+        o = default_opts(**opts)
+        rep = PcgReport()
+        inner = ctypes.c_int64(0)
+        st = lib().gpe_be_solve(self._h, self._field(V, "V", False), self._field(phi, "phi"), float(dt),
+                                int(bool(lambda_term)), ctypes.byref(o), float(inner_tol), ctypes.byref(inner),
+                                ctypes.byref(rep), _stream(stream))
+        _check(st)
+        d = rep.as_dict()
+        d["inner_iters"] = inner.value
+        return d
 
     def history(self, cap: int = 100000):
         buf = (ctypes.c_double * (8 * cap))()
