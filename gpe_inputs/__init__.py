@@ -197,6 +197,57 @@ def paper_initial(prob: Problem, kind: str, omega: float = 0.0) -> np.ndarray:
 # Named workloads
 # ----------------------------------------------------------------------------------------------
 
+def lattice_potential(prob: Problem, gammas=(1.0, 1.0, 1.0), kappas=(25.0, 25.0, 25.0),
+                      qs=(math.pi / 4, math.pi / 4, math.pi / 4)) -> np.ndarray:
+    """Harmonic plus optical-lattice trap of the paper's numerical section:
+    sum_a gamma_a^2 x_a^2 / 2 + kappa_a sin^2(q_a x_a) (reading: the harmonic part in the 1/2 form of
+    the paper's harmonic examples, and the lattice term periodic in x_a)."""
+    X = mesh(prob)
+    V = np.zeros(prob.shape)
+    for a in range(prob.dim):
+        V = V + 0.5 * (gammas[a] ** 2) * X[a] ** 2 + kappas[a] * np.sin(qs[a] * X[a]) ** 2
+    return np.ascontiguousarray(V, dtype=np.float64)
+
+
+def quartic_potential(prob: Problem, alpha: float = 1.2, kappa: float = 0.3, gamma_z: float = 3.0) -> np.ndarray:
+    """Harmonic plus quartic trap of the paper's numerical section (dim 2 or 3):
+    (1 - alpha) (x^2 + y^2) / 2 + kappa (x^2 + y^2)^2 / 4 (+ gamma_z^2 z^2 / 2 in 3-D).  With
+    alpha > 1 the quadratic part is repulsive and the quartic term confines, so rotations
+    Omega > 1 remain bound."""
+    if prob.dim < 2:
+        raise ValueError("the quartic trap is defined for dim 2 and 3")
+    X = mesh(prob)
+    r2 = X[0] ** 2 + X[1] ** 2
+    V = 0.5 * (1.0 - alpha) * r2 + 0.25 * kappa * r2 ** 2
+    if prob.dim == 3:
+        V = V + 0.5 * gamma_z ** 2 * X[2] ** 2
+    return np.ascontiguousarray(np.broadcast_to(V, prob.shape), dtype=np.float64)
+
+
+def thomas_fermi(prob: Problem, V: np.ndarray, gammas=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """Thomas-Fermi initial data of the paper's numerical section: sqrt(max(mu - V, 0) / beta),
+    normalised, with mu = (3 beta g_x)^{2/3} / 2 (1-D), (4 beta g_x g_y)^{1/2} / 2 (2-D),
+    (15 beta g_x g_y g_z)^{2/5} / 2 (3-D) for trap frequencies g (the harmonic-trap formula the paper
+    uses for every trap).  Needs beta > 0."""
+    b = prob.beta
+    if not b > 0.0:
+        raise ValueError("Thomas-Fermi data needs beta > 0")
+    g = gammas
+    mu = {1: 0.5 * (3.0 * b * g[0]) ** (2.0 / 3.0), 2: 0.5 * (4.0 * b * g[0] * g[1]) ** 0.5,
+          3: 0.5 * (15.0 * b * g[0] * g[1] * g[2]) ** 0.4}[prob.dim]
+    phi = np.sqrt(np.maximum(mu - V, 0.0) / b).astype(np.complex128)
+    return _unit(phi, prob)
+
+
+def workload_quartic_2d(M: int = 512, omega: float = 2.0, beta: float = 1000.0, L: float = 20.0):
+    """The paper's fast-rotation example in 2-D: harmonic plus quartic trap (alpha = 1.2,
+    kappa = 0.3), Thomas-Fermi start, on [-L, L]^2 with M^2 points (the paper: L = 20, h = 1/16,
+    i.e. M = 640; power-of-two grids here)."""
+    prob = Problem(2, (M, M), (L, L), beta, omega)
+    V = quartic_potential(prob)
+    return prob, V, thomas_fermi(prob, V)
+
+
 def workload_1d():
     """1-D, V = x^2/2 on [-16, 16], 256 points, beta = 250, Omega = 0."""
     prob = Problem(1, (256,), (16.0,), 250.0, 0.0)

@@ -497,3 +497,26 @@ def test_nested_grids_reproduce_the_multigrid_table():
     assert res.status == "converged"
     assert abs(res.E - multi[omega]["b"]) < 6e-5
     assert abs(res.E - fixed[omega]["b"]) > 0.2
+
+
+# ----------------------------------------------------------------------------------------------
+# The paper's trap families and Thomas-Fermi data (input recipes of its numerical section)
+# ----------------------------------------------------------------------------------------------
+
+def test_paper_traps_and_thomas_fermi_data():
+    from gpe_inputs import lattice_potential, quartic_potential, thomas_fermi
+    prob = Problem(2, (64, 64), (8.0, 8.0), 1000.0, 0.0)
+    x, y = mesh(prob)
+    r2 = x ** 2 + y ** 2
+    assert np.allclose(quartic_potential(prob, 1.2, 0.3), -0.1 * r2 + 0.075 * r2 ** 2, rtol=1e-14, atol=1e-12)
+    assert np.allclose(lattice_potential(prob, (1.0, 1.0), (25.0, 25.0), (math.pi / 4, math.pi / 4)),
+                       0.5 * r2 + 25.0 * (np.sin(math.pi * x / 4) ** 2 + np.sin(math.pi * y / 4) ** 2),
+                       rtol=1e-14, atol=1e-12)
+    V = harmonic_potential(prob)
+    tf = thomas_fermi(prob, V)
+    mu = 0.5 * math.sqrt(4.0 * 1000.0)
+    assert abs(O.norm(prob, tf) - 1.0) < 1e-13
+    assert np.all(tf[V >= mu] == 0.0) and np.all(np.abs(tf[V < mu - 1e-9]) > 0.0)
+    # a start the oracle's PCG takes to the ground state
+    res = O.pcg(prob, V, tf, tol_res=1e-6, max_iter=400)
+    assert res.status == "converged"
