@@ -132,15 +132,19 @@ struct OpProlong {
     static constexpr unsigned MAXMASK = 0;
     const C2<T>* f;
     C2<T>* out;
-    struct State { C2<T> f0[8]; };
-    __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&)[1]) const {
+    double hr, hi;  // e^{i pi / M} (host FP64) for the pass's line length M
+    struct State {};
+    __device__ void load(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1]) const {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) st.f0[s] = v[s] = f[lc.at(s)];
+        for (int s = 0; s < 8; ++s) v[s] = f[lc.at(s)];
     }
+    // e^{i pi p / M} from the transform's table tw[e] = e^{-2 pi i e / M}: conj(tw[floor(p/2) mod M]),
+    // times e^{i pi / M} for odd p.
     template <int LG>
     __device__ void spectral(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
-                             const C2<T>*) const {
-        const double inv = ldexp(1.0, -lc.lg);  // 1/M, exact
+                             const C2<T>* tw) const {
+        const T inv = (T)ldexp(1.0, -lc.lg);  // 1/M, exact
+        const C2<T> half{(T)hr, (T)hi};
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const int j = lc.k(s);
@@ -148,24 +152,27 @@ struct OpProlong {
             if (2 * p == -lc.M) {
                 v[s] = C2<T>{(T)0, (T)0};
             } else {
-                double sn, cs;
-                sincospi((double)p * inv, &sn, &cs);
-                v[s] = mul(v[s], C2<T>{(T)(cs * inv), (T)(sn * inv)});
+                const int q = (p - (p & 1)) >> 1;
+                const C2<T> t = tw[q < 0 ? q + lc.M : q];
+                C2<T> m{t.x, -t.y};
+                if (p & 1) m = mul(m, half);
+                v[s] = scl(mul(v[s], m), inv);
             }
         }
     }
-    __device__ void store(const Geo& g, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&)[1]) const {
+    __device__ void store(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1]) const {
         // source offset s (within its instance) -> even output offset: x: 2s; y: 2s - x;
         // z: 2s - (y n_x + x); the odd neighbour is one output step further along AX.
         const int64_t nx = g.n[0], nxy = (int64_t)g.n[0] * g.n[1];
         const int64_t keep = AX == 0 ? 0 : (AX == 1 ? (int64_t)lc.i1 : (int64_t)lc.i2 * nx + lc.i1);
         const int64_t step = AX == 0 ? 1 : (AX == 1 ? nx : nxy);
         C2<T>* o = out + 2 * lc.off_b;
+        const int64_t e0 = 2 * (lc.at(0) - lc.off_b) - keep;  // the points of a thread are TPL apart
+        const int64_t de = 2 * (int64_t)lc.TPL * lc.stride;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const int64_t e = 2 * (lc.at(s) - lc.off_b) - keep;
-            o[e] = st.f0[s];
-            o[e + step] = v[s];
+            o[e0 + s * de] = f[lc.at(s)];  // re-read (cached): keeping the inputs across the transforms
+            o[e0 + s * de + step] = v[s];  // put them in scratch memory in FP64
         }
     }
 };
@@ -183,6 +190,12 @@ static Geo doubled_upto(const Geo& g, int upto) {
     return d;
 }
 
+template <typename T, int AX>
+static OpProlong<T, AX> prolong_op(const Geo& g, const C2<T>* src, C2<T>* dst) {
+    const double a = 3.141592653589793238462643383279502884 / g.n[AX];
+    return OpProlong<T, AX>{src, dst, std::cos(a), std::sin(a)};
+}
+
 template <typename T>
 static hipError_t prolong_t(const Geo& g, const Twiddles& tw, const void* in, void* out, void* tmp, hipStream_t s) {
     const bool f64 = sizeof(T) == 8;
@@ -191,16 +204,16 @@ static hipError_t prolong_t(const Geo& g, const Twiddles& tw, const void* in, vo
     const C2<T>* src = (const C2<T>*)in;
     C2<T>* dst = (C2<T>*)out;
     C2<T>* t = (C2<T>*)tmp;
-    if (g.dim == 1) return launch_pass<T, 0>(g, 1, tw.get(0, f64), OpProlong<T, 0>{src, dst}, none, s);
+    if (g.dim == 1) return launch_pass<T, 0>(g, 1, tw.get(0, f64), prolong_op<T, 0>(g, src, dst), none, s);
     // 2-D: x into tmp (2N), y into out.  3-D: x into the last quarter of out, y into tmp (4N),
     // z into out (the x result is dead by then; passes on one stream run in order).
     C2<T>* xo = g.dim == 2 ? t : dst + 6 * g.N;
-    if ((e = launch_pass<T, 0>(g, 1, tw.get(0, f64), OpProlong<T, 0>{src, xo}, none, s)) != hipSuccess) return e;
+    if ((e = launch_pass<T, 0>(g, 1, tw.get(0, f64), prolong_op<T, 0>(g, src, xo), none, s)) != hipSuccess) return e;
     const Geo g1 = doubled_upto(g, 1);
-    if (g.dim == 2) return launch_pass<T, 1>(g1, 1, tw.get(1, f64), OpProlong<T, 1>{xo, dst}, none, s);
-    if ((e = launch_pass<T, 1>(g1, 1, tw.get(1, f64), OpProlong<T, 1>{xo, t}, none, s)) != hipSuccess) return e;
+    if (g.dim == 2) return launch_pass<T, 1>(g1, 1, tw.get(1, f64), prolong_op<T, 1>(g1, xo, dst), none, s);
+    if ((e = launch_pass<T, 1>(g1, 1, tw.get(1, f64), prolong_op<T, 1>(g1, xo, t), none, s)) != hipSuccess) return e;
     const Geo g2 = doubled_upto(g, 2);
-    return launch_pass<T, 2>(g2, 1, tw.get(2, f64), OpProlong<T, 2>{t, dst}, none, s);
+    return launch_pass<T, 2>(g2, 1, tw.get(2, f64), prolong_op<T, 2>(g2, t, dst), none, s);
 }
 
 hipError_t op_prolong(const Geo& g, bool f64, const Twiddles& tw, const void* in, void* out, void* tmp, hipStream_t s) {

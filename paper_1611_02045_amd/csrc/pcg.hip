@@ -419,7 +419,9 @@ using IntakeA = IntakeAbsorb<A_K, kARowsPerThread>;
 // ---------------------------------------------------------------------------------------------
 template <typename T, bool ONE>
 struct OpResid {
-    static constexpr bool FWD = true, INV = ONE, SCALARS = true, PREFETCH = true, WIDE = true;
+    // FP32 2-D/3-D: capped at four workgroups per CU despite a small spill (measured faster than the
+    // second round of workgroups the unconstrained allocation leaves on the batched 512^2 step)
+    static constexpr bool FWD = true, INV = ONE, SCALARS = true, PREFETCH = true, WIDE = sizeof(T) == 8 || ONE;
     static constexpr int K = A_K;
     static constexpr unsigned MAXMASK = A_MAXMASK;
     IterFields<T> f;
