@@ -154,10 +154,14 @@ int gpe_pcg_solve(gpe_plan_t* plan, const void* V, void* phi_inout, const gpe_pc
  * halvings_n, restarted_n}; returns the number of rows written (>= 0) or an error. */
 int gpe_pcg_history(gpe_plan_t* plan, double* hist, int cap);
 
-/* Independent solves of `count` problems (possibly different grids, beta, omega, L) in one
- * iteration loop; instances of equal grid share each kernel launch and converged instances
- * are masked out.  V[i], phi_inout[i]: device fields of instance i in its own layout and in
- * the type `dtype`.  reports: host array of `count`.  Returns the worst status.  Synchronises. */
+/* Independent solves of `count` problems (possibly different grids, beta, omega, L); instances
+ * of equal grid share each kernel launch and converged instances are masked out.  The instances
+ * of a grid are split into two parts solved concurrently on the caller's stream and on a second
+ * stream (default priority) that the call creates, each driven by its own host thread; the
+ * second stream first waits for the work already queued on the caller's stream.  Results do not
+ * depend on the split.  V[i], phi_inout[i]: device fields of instance i in its own layout and
+ * in the type `dtype`.  reports: host array of `count`.  Returns the worst status.
+ * Synchronises both streams before returning. */
 int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void* const* V,
                           void* const* phi_inout, const gpe_pcg_opts_t* opts,
                           gpe_pcg_report_t* reports, void* stream);

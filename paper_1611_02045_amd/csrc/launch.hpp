@@ -1,6 +1,9 @@
 // Host-side launch helpers for directional passes.
 #pragma once
 
+#include <atomic>
+#include <mutex>
+
 #include <algorithm>
 
 #include <hip/hip_ext.h>
@@ -11,15 +14,15 @@ namespace gpe {
 
 // Compute units of the current device (queried once per device).
 inline int device_cus() {
-    static int cached[16] = {};
+    static std::atomic<int> cached[16] = {};  // solves may run on several host threads
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 256;
-    if (cached[dev] == 0) {
-        int n = 0;
+    int n = cached[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-        cached[dev] = n;
+        cached[dev].store(n, std::memory_order_relaxed);
     }
-    return cached[dev];
+    return n;
 }
 
 // Optional start/stop events a launch records around its own execution (per-kernel timing).
@@ -108,15 +111,14 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
                            pass_kernel<T, AX, Op, kMaxPassThreads, false, kLG>,
                            pass_kernel<T, AX, Op, kMaxPassThreads, true, kLG>};
     const K kern = variants[(ct ? 2 : 0) + (early ? 1 : 0)];
-    static bool attr_set = false;  // one attribute call per instantiation set
-    if (!attr_set) {
+    static std::once_flag attr_once;  // one attribute call per instantiation set (thread-safe)
+    std::call_once(attr_once, [&] {
         // Raise the dynamic-LDS cap once; a runtime that does not need it may refuse harmlessly.
         for (K k : variants)
             if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPassLdsBudget) !=
                 hipSuccess)
                 (void)hipGetLastError();
-        attr_set = true;
-    }
+    });
     launch_timed(ev, kern, dim3((unsigned)blocks), dim3(threads), lds, s, g, C, (const C2<T>*)tw, op, pr);
     return hipGetLastError();
 }
