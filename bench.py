@@ -5,7 +5,8 @@ Workload: 2-D 512^2 grid on [-16, 16]^2, V = (x^2 + y^2)/2, beta = 1000, Omega =
 vortex-seed starts (the several initial data the paper runs per parameter set, keeping the lowest
 energy), PCG with the symmetric combined preconditioner, stop at ||H phi - lambda phi||_inf <= 1e-8
 for every start.  One step = the eight starts solved together from resident copies as one batched
-PCG solve with per-instance convergence masks (every stage of the hot path: transforms, H apply,
+PCG solve with per-instance convergence masks, run by the library as two parts of four on two
+streams (every stage of the hot path: transforms, H apply,
 preconditioner, reductions, direction, line search, retraction, convergence control, precision
 switch).  At Omega = 0.9 the iteration count to 1e-8 depends strongly on the start (soft
 vortex-lattice modes): a step lasts as long as its slowest start.
@@ -298,8 +299,8 @@ def main():
         "data": "synthetic (seeded vortex-seed starts, analytic trap)",
         "config": {"workload": f"2D 512^2 rotating GPE on [-16,16]^2, V=(x^2+y^2)/2, beta=1000, Omega=0.9, "
                                f"{S} seeded starts solved as one batched PCG (combined preconditioner, "
-                               f"per-instance masks) until every start has ||r||_inf <= 1e-8; value = seconds "
-                               f"per step (the whole batch)",
+                               f"per-instance masks, two parts on two streams) until every start has "
+                               f"||r||_inf <= 1e-8; value = seconds per step (the whole batch)",
                    "grid": [512, 512], "beta": 1000.0, "omega": 0.9, "tol": tol, "starts": S,
                    "seeds": list(SEEDS_2D_512_SET)},
         "time_to_tol_fp64_s": mean(t_fp64),
