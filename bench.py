@@ -13,7 +13,8 @@ vortex-lattice modes): a step lasts as long as its slowest start.
 
 Printed (one JSON line on stdout): the mixed FP32/FP64 time-to-1e-8 of a step as `value`, beside the
 FP64 step time, each start solved alone (mixed and FP64), the same starts on nested grids 64^2 ->
-512^2 (the paper's multigrid preparation of initial data), H_phi applies/s, PCG iterations/s, the
+512^2 (the paper's multigrid preparation of initial data), the 64-instance sweep of mixed grids,
+H_phi applies/s, PCG iterations/s, the
 dominant kernel's roofline figure (kernel-only HIP event timings of the step's configuration, HBM
 traffic from the committed counter summary) and the CPU oracle timed on the host (bounded sample,
 extrapolated).
@@ -127,6 +128,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the one-start-at-a-time solves")
     ap.add_argument("--no-nested", action="store_true", help="skip the nested-grid solves")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 64-instance sweep")
     ap.add_argument("--tol-coarse", type=float, default=1e-5, help="residual tolerance of the coarse nested grids")
     ap.add_argument("--profile-iters", type=int, default=30)
     ap.add_argument("--profile-only", action="store_true",
@@ -242,6 +244,30 @@ def main():
             log(f"[bench] nested {tag}: {mean(secs):.4f} s/step, iterations per level (max) "
                 f"{[max(r['iters'] for r in lv) for lv in lrep]}")
 
+    # the 64-instance sweep (Omega ~ U[0, 0.95], beta ~ U{100, 500, 1000, 2000}, M ~ U{128, 256, 512},
+    # boxes from the Thomas-Fermi radius, vortex-seed starts) as one batched solve to 1e-8
+    sweep = None
+    if not args.no_sweep:
+        import collections
+        from gpe_inputs import batch_instances
+        inst = batch_instances(64)
+        sw_probs = [bi.prob for bi in inst]
+        sw_V = [torch.from_numpy(bi.V).to("cuda") for bi in inst]
+        sweep = {"instances": len(inst), "grids": dict(collections.Counter(f"{bi.prob.n[0]}^2" for bi in inst))}
+        for tag, opts in (("mixed", mixed), ("fp64", fp64)):
+            phis = [torch.from_numpy(bi.phi0).to("cuda") for bi in inst]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, sw_reps = gpe.pcg_solve_batched(sw_probs, sw_V, phis, "f64", **opts)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            by = collections.defaultdict(int)
+            for bi, r in zip(inst, sw_reps):
+                by[f"{bi.prob.n[0]}^2"] = max(by[f"{bi.prob.n[0]}^2"], r["iters"])
+            sweep[tag] = {"s": sec, "max_iters_per_grid": dict(by), "all_converged": all(r["status"] == 0 for r in sw_reps),
+                          "total_iters": sum(r["iters"] for r in sw_reps)}
+            log(f"[bench] sweep of 64 {tag}: {sec:.3f} s, max iterations per grid {dict(by)}")
+
     # H_phi applies/s (single field and a batch of 32 fields, FP64 and FP32)
     log("[bench] H applies")
     plan64 = gpe.Plan.from_problem(prob, "f64")
@@ -309,6 +335,7 @@ def main():
         "iters_fp64": it_fp64,
         "single_start": single,
         "nested_grids": nested,
+        "sweep_64": sweep,
         "pcg_iters_per_s_step": {"mixed": max(it_mixed) / mean(t_mixed), "fp64": max(it_fp64) / mean(t_fp64)},
         "h_applies_per_s": {"fp64": ap64, "fp32": ap32, "fp64_batch32": apb64, "fp32_batch32": apb32},
         "h_apply_batch32_hbm_gbs": {

@@ -156,10 +156,10 @@ int gpe_pcg_history(gpe_plan_t* plan, double* hist, int cap);
 
 /* Independent solves of `count` problems (possibly different grids, beta, omega, L); instances
  * of equal grid share each kernel launch and converged instances are masked out.  The instances
- * of a grid are split into two parts solved concurrently on the caller's stream and on a second
- * stream (default priority) that the call creates, each driven by its own host thread; the
- * second stream first waits for the work already queued on the caller's stream.  Results do not
- * depend on the split.  V[i], phi_inout[i]: device fields of instance i in its own layout and
+ * of a grid are split into two parts, and the parts of all grids are solved concurrently, each
+ * on its own stream (the caller's for the first, default-priority streams the call creates for
+ * the others) driven by its own host thread; the created streams first wait for the work already
+ * queued on the caller's stream.  Results do not depend on the split.  V[i], phi_inout[i]: device fields of instance i in its own layout and
  * in the type `dtype`.  reports: host array of `count`.  Returns the worst status.
  * Synchronises both streams before returning. */
 int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void* const* V,

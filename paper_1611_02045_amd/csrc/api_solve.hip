@@ -289,6 +289,71 @@ int solve_group(int B, const gpe_problem_t* gp, bool in_f64, const void* const* 
     return st;
 }
 
+// Runs task(k, stream_k) for k = 0 .. n-1 concurrently: task 0 on the caller's thread and stream,
+// the others each on a stream (default priority) and host thread of their own, after the work
+// already queued on the caller's stream.  Returns a HIP or argument error of any task, else the
+// worst status, with the message moved to the caller's thread.
+template <class F>
+int run_concurrent(int n, hipStream_t s, F task) {
+    if (n < 2) return task(0, s);
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    std::vector<hipStream_t> ss(n, s);
+    int created = 1;
+    hipError_t e = hipEventRecord(ev, s);  // the inputs are ready on the caller's stream
+    for (int k = 1; k < n && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&ss[k], hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            created = k + 1;
+            e = hipStreamWaitEvent(ss[k], ev, 0);
+        }
+    }
+    std::vector<int> st(n, GPE_OK);
+    std::vector<std::string> err(n);
+    if (e == hipSuccess) {
+        auto run = [&](int k) {
+            st[k] = task(k, ss[k]);
+            if (st[k] < 0) err[k] = gpe_last_error();  // the message is thread-local
+        };
+        std::vector<std::thread> th;
+        for (int k = 1; k < n; ++k) {
+            try {
+                th.emplace_back([&, k] {
+                    (void)hipSetDevice(dev);  // the current device is per host thread
+                    run(k);
+                });
+            } catch (...) {
+                run(k);  // no thread: this task runs before the caller's instead of beside it
+            }
+        }
+        run(0);
+        for (auto& t : th) t.join();
+    }
+    for (int k = 1; k < created; ++k) {
+        (void)hipStreamSynchronize(ss[k]);
+        (void)hipStreamDestroy(ss[k]);
+    }
+    (void)hipEventDestroy(ev);
+    HIPCHK(e);
+    // a HIP or argument error first (the tasks' outputs are then unreliable), else the worst status
+    // (per-instance reports stay valid for the others), with the message of the task that set it
+    for (int k = 0; k < n; ++k)
+        if (st[k] == GPE_EHIP || st[k] == GPE_EINVAL) {
+            set_error(err[k]);
+            return st[k];
+        }
+    int worst = GPE_OK, from = -1;
+    for (int k = 0; k < n; ++k)
+        if (worse_status(worst, st[k]) != worst) {
+            worst = worse_status(worst, st[k]);
+            from = k;
+        }
+    if (worst < 0 && from >= 0) set_error(err[from]);
+    return worst;
+}
+
 // Instances of one grid solved as kSolveStreams independent parts, each on its own stream driven by
 // its own host thread.  A part's kernels then run while another part's are in a different phase
 // (one loading fields, the other transforming), which a single batched launch cannot do: every
@@ -301,58 +366,11 @@ constexpr int kSolveStreams = 2;
 int solve_group_split(int B, const gpe_problem_t* gp, bool in_f64, const void* const* gV, void* const* gphi,
                       const gpe_pcg_opts_t& o, gpe_pcg_report_t* rep, hipStream_t s) {
     const int P = std::min(B, kSolveStreams);
-    if (P < 2) return solve_group(B, gp, in_f64, gV, gphi, o, rep, s);
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
-    hipEvent_t ev;
-    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    std::vector<hipStream_t> ss(P, s);
-    int created = 1;
-    hipError_t e = hipEventRecord(ev, s);  // the inputs are ready on the caller's stream
-    for (int k = 1; k < P && e == hipSuccess; ++k) {
-        e = hipStreamCreateWithFlags(&ss[k], hipStreamNonBlocking);  // default priority
-        if (e == hipSuccess) {
-            created = k + 1;
-            e = hipStreamWaitEvent(ss[k], ev, 0);
-        }
-    }
-    std::vector<int> st(P, GPE_OK), b0(P + 1, 0);
-    std::vector<std::string> err(P);
-    if (e == hipSuccess) {
-        for (int k = 0; k <= P; ++k) b0[k] = (int)((int64_t)B * k / P);
-        auto part = [&](int k) {
-            st[k] = solve_group(b0[k + 1] - b0[k], gp + b0[k], in_f64, gV + b0[k], gphi + b0[k], o, rep + b0[k], ss[k]);
-            if (st[k] < 0) err[k] = gpe_last_error();  // the message is thread-local
-        };
-        std::vector<std::thread> th;
-        for (int k = 1; k < P; ++k) {
-            try {
-                th.emplace_back([&, k] {
-                    (void)hipSetDevice(dev);  // the device is per host thread
-                    part(k);
-                });
-            } catch (...) {
-                part(k);  // no thread: this part runs before the caller's part instead of beside it
-            }
-        }
-        part(0);
-        for (auto& t : th) t.join();
-    }
-    for (int k = 1; k < created; ++k) {
-        (void)hipStreamSynchronize(ss[k]);
-        (void)hipStreamDestroy(ss[k]);
-    }
-    (void)hipEventDestroy(ev);
-    HIPCHK(e);
-    int worst = GPE_OK;
-    for (int k = 0; k < P; ++k) {
-        if (st[k] < 0) {
-            set_error(err[k]);
-            return st[k];
-        }
-        worst = worse_status(worst, st[k]);
-    }
-    return worst;
+    std::vector<int> b0(P + 1);
+    for (int k = 0; k <= P; ++k) b0[k] = (int)((int64_t)B * k / P);
+    return run_concurrent(P, s, [&](int k, hipStream_t sk) {
+        return solve_group(b0[k + 1] - b0[k], gp + b0[k], in_f64, gV + b0[k], gphi + b0[k], o, rep + b0[k], sk);
+    });
 }
 
 }  // namespace
@@ -491,27 +509,30 @@ int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void
         return std::make_tuple(p.dim, p.n[0], p.dim > 1 ? p.n[1] : 1, p.dim > 2 ? p.n[2] : 1);
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
-    int worst = GPE_OK;
-    size_t pos = 0;
-    while (pos < order.size()) {
-        size_t end = pos;
-        while (end < order.size() && key(order[end]) == key(order[pos])) ++end;
-        const int B = (int)(end - pos);
-        std::vector<gpe_problem_t> gp(B);
-        std::vector<const void*> gV(B);
-        std::vector<void*> gphi(B);
-        for (int b = 0; b < B; ++b) {
-            gp[b] = probs[order[pos + b]];
-            gV[b] = V[order[pos + b]];
-            gphi[b] = phi_inout[order[pos + b]];
-        }
-        std::vector<gpe_pcg_report_t> rep(B);
-        st = solve_group_split(B, gp.data(), dtype == GPE_F64, gV.data(), gphi.data(), *opts, rep.data(), s);
-        if (st == GPE_EHIP || st == GPE_EINVAL) return st;
-        for (int b = 0; b < B; ++b) reports[order[pos + b]] = rep[b];
-        worst = worse_status(worst, st);
-        pos = end;
+    // grid groups [first[g], first[g+1]) of `order`, solved concurrently (a latency-bound group of
+    // small grids then runs beside a bandwidth-bound group of large ones)
+    std::vector<size_t> first{0};
+    for (size_t i = 1; i < order.size(); ++i)
+        if (key(order[i]) != key(order[i - 1])) first.push_back(i);
+    first.push_back(order.size());
+    const int G = (int)first.size() - 1;
+    const bool in_f64 = dtype == GPE_F64;
+    std::vector<gpe_problem_t> gp(count);
+    std::vector<const void*> gV(count);
+    std::vector<void*> gphi(count);
+    std::vector<gpe_pcg_report_t> rep(count);
+    for (int i = 0; i < count; ++i) {
+        gp[i] = probs[order[i]];
+        gV[i] = V[order[i]];
+        gphi[i] = phi_inout[order[i]];
     }
+    const int worst = run_concurrent(G, s, [&](int g, hipStream_t sg) {
+        const size_t a = first[g];
+        return solve_group_split((int)(first[g + 1] - a), gp.data() + a, in_f64, gV.data() + a, gphi.data() + a,
+                                 *opts, rep.data() + a, sg);
+    });
+    if (worst == GPE_EHIP || worst == GPE_EINVAL) return worst;
+    for (int i = 0; i < count; ++i) reports[order[i]] = rep[i];
     return worst;
 }
 
