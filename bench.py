@@ -129,6 +129,7 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="skip the one-start-at-a-time solves")
     ap.add_argument("--no-nested", action="store_true", help="skip the nested-grid solves")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 64-instance sweep")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 1-D, 2-D 256^2 and 3-D single solves")
     ap.add_argument("--tol-coarse", type=float, default=1e-5, help="residual tolerance of the coarse nested grids")
     ap.add_argument("--profile-iters", type=int, default=30)
     ap.add_argument("--profile-only", action="store_true",
@@ -268,6 +269,41 @@ def main():
                           "total_iters": sum(r["iters"] for r in sw_reps)}
             log(f"[bench] sweep of 64 {tag}: {sec:.3f} s, max iterations per grid {dict(by)}")
 
+    # the other single-solve configurations of the workload set: 1-D 256 points (FP64 to 1e-10, and
+    # beta = 0 whose exact energy is 1/2), 2-D 256^2 at Omega = 0.9 (FP64 and mixed to 1e-8), 3-D 128^3
+    # at Omega = 0.8 (complex64 fields with FP64 scalars, then the FP64 refinement, to 1e-8)
+    configs = None
+    if not args.no_configs:
+        from gpe_inputs import workload_1d, workload_2d, workload_3d
+        configs = {}
+
+        def timed_solve(p, Vn, phin, dtype, **opts):
+            pl = gpe.Plan.from_problem(p, dtype)
+            cd = torch.complex128 if dtype == "f64" else torch.complex64
+            rd = torch.float64 if dtype == "f64" else torch.float32
+            Vd = torch.from_numpy(Vn).to("cuda", rd)
+            ph = torch.from_numpy(phin).to("cuda", cd)
+            pl.pcg_solve(Vd, ph.clone(), **dict(opts, max_iter=50))  # warm the plan
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = pl.pcg_solve(Vd, ph, **opts)
+            torch.cuda.synchronize()
+            return {"s": time.perf_counter() - t0, "iters": r["iters"], "E": r["E"], "res_inf": r["res_inf"],
+                    "status": r["status_name"]}
+
+        p1, V1, f1 = workload_1d()
+        configs["1d_256_fp64_tol1e-10"] = timed_solve(p1, V1, f1, "f64", tol=1e-10)
+        p0 = type(p1)(1, (256,), (16.0,), 0.0, 0.0)
+        configs["1d_256_beta0_fp64"] = timed_solve(p0, V1, f1, "f64", tol=1e-10)
+        configs["1d_256_beta0_fp64"]["E_exact"] = 0.5
+        p2, V2, f2 = workload_2d(256)
+        configs["2d_256_fp64"] = timed_solve(p2, V2, f2, "f64", tol=1e-8, max_iter=200000)
+        configs["2d_256_mixed"] = timed_solve(p2, V2, f2, "f64", tol=1e-8, max_iter=200000, precision="mixed")
+        p3, V3, f3 = workload_3d(128)
+        configs["3d_128_mixed"] = timed_solve(p3, V3, f3, "f64", tol=1e-8, max_iter=200000, precision="mixed")
+        for k, v in configs.items():
+            log(f"[bench] config {k}: {v['s']:.4f} s, {v['iters']} iterations, E = {v['E']:.10f}, {v['status']}")
+
     # H_phi applies/s (single field and a batch of 32 fields, FP64 and FP32)
     log("[bench] H applies")
     plan64 = gpe.Plan.from_problem(prob, "f64")
@@ -336,6 +372,7 @@ def main():
         "single_start": single,
         "nested_grids": nested,
         "sweep_64": sweep,
+        "other_configs": configs,
         "pcg_iters_per_s_step": {"mixed": max(it_mixed) / mean(t_mixed), "fp64": max(it_fp64) / mean(t_fp64)},
         "h_applies_per_s": {"fp64": ap64, "fp32": ap32, "fp64_batch32": apb64, "fp32_batch32": apb32},
         "h_apply_batch32_hbm_gbs": {
