@@ -123,6 +123,10 @@ typedef struct gpe_pcg_opts {
     int32_t refresh_every; /* recompute L phi from phi every this many iterations (0 = never) */
     int32_t check_every;   /* iterations queued between convergence polls */
     int32_t record_history;/* nonzero: keep per-iteration scalars (see gpe_pcg_history) */
+    int32_t use_graph;     /* nonzero: after the first chunk, replay the chunk of check_every
+                            * iterations as a captured HIP graph (needs an even check_every; used
+                            * by single solves and single-instance batches, whose one host thread
+                            * drives the solve) */
 } gpe_pcg_opts_t;
 
 typedef struct gpe_pcg_report {
@@ -139,7 +143,7 @@ typedef struct gpe_pcg_report {
 } gpe_pcg_report_t;
 
 /* Fill *opts with defaults: PCG, P_C, tol 1e-8, 20000 iterations, FP64, Polak-Ribiere,
- * switch_res 1e-6, theta_default 0.1, 30 halvings, refresh every 50, poll every 16. */
+ * switch_res 1e-6, theta_default 0.1, 30 halvings, refresh every 50, poll every 16, graph replay on. */
 void gpe_pcg_opts_default(gpe_pcg_opts_t* opts);
 
 /* Ground state by PG / PCG on the unit sphere (Algorithms 1-2 with the step control of

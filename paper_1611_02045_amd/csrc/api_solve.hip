@@ -48,6 +48,7 @@ int run(BatchWork& w, int B, IterFields<T> f, std::vector<Scal>& hs, const gpe_p
     pa.precond = o.precond;
     pa.check_every = o.check_every;
     pa.refresh_every = o.refresh_every;
+    pa.use_graph = o.use_graph != 0;
     pa.final_f_r_is_rp = false;
     HIPCHK(run_phase<T>(pa, f, hs, s));
     return GPE_OK;
@@ -393,6 +394,7 @@ void gpe_pcg_opts_default(gpe_pcg_opts_t* o) {
     o->refresh_every = 50;
     o->check_every = 16;
     o->record_history = 0;
+    o->use_graph = 1;
 }
 
 int gpe_pcg_solve(gpe_plan_t* plan, const void* V, void* phi_inout, const gpe_pcg_opts_t* opts,
@@ -526,10 +528,14 @@ int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void
         gV[i] = V[order[i]];
         gphi[i] = phi_inout[order[i]];
     }
+    // Graph capture runs only where a single host thread drives the solve: HIP refuses the
+    // set-up calls of other threads (allocation, tables) while one thread captures.
+    gpe_pcg_opts_t o = *opts;
+    if (G > 1 || (int)(first[1] - first[0]) > 1) o.use_graph = 0;
     const int worst = run_concurrent(G, s, [&](int g, hipStream_t sg) {
         const size_t a = first[g];
         return solve_group_split((int)(first[g + 1] - a), gp.data() + a, in_f64, gV.data() + a, gphi.data() + a,
-                                 *opts, rep.data() + a, sg);
+                                 o, rep.data() + a, sg);
     });
     if (worst == GPE_EHIP || worst == GPE_EINVAL) return worst;
     for (int i = 0; i < count; ++i) reports[order[i]] = rep[i];

@@ -209,12 +209,73 @@ static hipError_t zero_cg_memory(IterFields<T>& f, int64_t BN, hipStream_t s) {
 // ---------------------------------------------------------------------------------------------
 // One phase for B instances of one grid.
 // ---------------------------------------------------------------------------------------------
+// A non-blocking stream of default priority ordered after the work queued on another stream;
+// synchronised and destroyed with the object.
+struct PrivateStream {
+    hipStream_t s = nullptr;
+    hipError_t create_after(hipStream_t other) {
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            s = nullptr;
+            return e;
+        }
+        hipEvent_t ev;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+        e = hipEventRecord(ev, other);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+        (void)hipEventDestroy(ev);
+        return e;
+    }
+    ~PrivateStream() {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    }
+};
+
+// An instantiated graph captured from work queued on one stream (thread-local capture mode: other
+// host threads may allocate or launch meanwhile).  Captures only kernel launches: no memory-set or
+// copy nodes.
+struct GraphExec {
+    hipGraphExec_t exec = nullptr;
+    template <class F>
+    hipError_t capture(hipStream_t s, F enqueue) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        hipError_t qe = enqueue();
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s, &g);
+        if (qe != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return qe != hipSuccess ? qe : e;
+        }
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) exec = nullptr;
+        return e;
+    }
+    ~GraphExec() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
 template <typename T>
-hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, hipStream_t s) {
+hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, hipStream_t s_caller) {
     const Geo& g = pa.g;
     const int B = pa.B;
     const int64_t N = g.N;
     hipError_t e;
+    // Graph capture is not possible on the legacy default stream (the usual caller's stream): with
+    // graphs the phase runs on a private stream that first waits for the caller's queued work; the
+    // loop below ends with a synchronisation of that stream, so nothing is left queued on it.
+    const bool want_graph = pa.use_graph && pa.check_every % 2 == 0;
+    PrivateStream own;
+    hipStream_t s = s_caller;
+    if (want_graph) {
+        if ((e = own.create_after(s_caller)) != hipSuccess) return e;
+        s = own.s;
+    }
     // scalars to the device
     // three versioned state slots (after the step, after the convergence test, after the direction);
     // an iteration starts from S_dir
@@ -251,14 +312,35 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
     int64_t queued = 0;
     int64_t max_iter = 0;
     for (int b = 0; b < B; ++b) max_iter = std::max<int64_t>(max_iter, host_S[b].max_iter);
+    // A chunk of check_every iterations launches the same kernels with the same arguments every
+    // time (the r / r_{n-1} roles swap each iteration, so an even chunk ends where it started): after
+    // one chunk ran eagerly, the next is captured into a graph and every later chunk replays it.
+    GraphExec graph;
+    int64_t chunks = 0;
     for (;;) {
         // host-side guard: every queued iteration either advances n or finishes the instance
         if (queued > 2 * max_iter + 4 * (int64_t)pa.check_every + 64) return hipErrorUnknown;
         queued += pa.check_every;
-        for (int k = 0; k < pa.check_every; ++k) {
-            if ((e = enqueue_iteration<T>(c, s)) != hipSuccess) return e;
-            std::swap(c.f.r, c.f.rp);
+        if (!graph.exec && want_graph && chunks >= 1) {
+            if ((e = graph.capture(s, [&] {
+                     for (int k = 0; k < pa.check_every; ++k) {
+                         hipError_t ee = enqueue_iteration<T>(c, s);
+                         if (ee != hipSuccess) return ee;
+                         std::swap(c.f.r, c.f.rp);
+                     }
+                     return hipSuccess;
+                 })) != hipSuccess)
+                return e;
         }
+        if (graph.exec) {
+            if ((e = hipGraphLaunch(graph.exec, s)) != hipSuccess) return e;
+        } else {
+            for (int k = 0; k < pa.check_every; ++k) {
+                if ((e = enqueue_iteration<T>(c, s)) != hipSuccess) return e;
+                std::swap(c.f.r, c.f.rp);
+            }
+        }
+        ++chunks;
         since_refresh += pa.check_every;
         if ((e = hipMemcpyAsync(host_S.data(), S_dir, sizeof(Scal) * B, hipMemcpyDeviceToHost, s)) != hipSuccess)
             return e;

@@ -17,6 +17,7 @@ struct PhaseArgs {
     int precond;
     int check_every;
     int refresh_every;
+    bool use_graph = false;  // replay chunks of check_every iterations as a captured graph
     bool final_f_r_is_rp;
 };
 

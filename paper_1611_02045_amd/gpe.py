@@ -38,7 +38,7 @@ class PcgOpts(ctypes.Structure):
                 ("tol_energy", ctypes.c_double), ("max_iter", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("beta_rule", ctypes.c_int32), ("switch_res", ctypes.c_double), ("theta_default", ctypes.c_double),
                 ("max_halvings", ctypes.c_int32), ("refresh_every", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("record_history", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("record_history", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class PcgReport(ctypes.Structure):

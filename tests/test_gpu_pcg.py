@@ -215,3 +215,46 @@ def test_trajectory_512_lines_single_and_batched(torch_gpu):
     for r, ref in zip(reps, refs):
         assert r["status"] == 1 and r["iters"] == iters
         assert abs(r["E"] - ref.E) < 1e-11 * abs(ref.E)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("key", sorted(CASES))
+def test_graph_replay_matches_eager_launches(torch_gpu, key, precision):
+    """Chunks of iterations replayed from a captured HIP graph (with the solver's own host polls,
+    drift refreshes and precision switch between the replays) give the very same trajectory as
+    launching every kernel: identical iteration counts, energies and final fields, bit for bit."""
+    prob, V, phi0 = _inputs(key)
+    print(f"graph replay {key} {precision}", flush=True)
+    runs = {}
+    for g in (0, 1):
+        runs[g] = _gpu_solve(torch_gpu, prob, V, phi0, tol=1e-10, max_iter=3000, precision=precision,
+                             use_graph=g, refresh_every=48)
+    (r0, f0, _), (r1, f1, _) = runs[0], runs[1]
+    assert r0["status"] == 0 and r1["status"] == 0
+    assert r0["iters"] == r1["iters"] and r0["iters_fp32"] == r1["iters_fp32"]
+    assert r0["E"] == r1["E"]
+    assert np.array_equal(f0, f1)
+
+
+def test_graph_option_batched_matches_eager(torch_gpu):
+    """The batched solve (two parts on two streams and threads, which launch eagerly whatever the
+    option) gives identical per-instance results with the graph option on and off."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    probs, Vs, starts = [], [], []
+    for i, (beta, om) in enumerate([(50.0, 0.2), (100.0, 0.5), (200.0, 0.6), (80.0, 0.0)]):
+        p = Problem(2, (64, 64), (8.0, 8.0), beta, om)
+        probs.append(p)
+        Vs.append(_dev(torch, harmonic_potential(p)))
+        starts.append(vortex_seed_2d(p, 11 + i))
+    out = {}
+    for g in (0, 1):
+        phis = [_dev(torch, s) for s in starts]
+        st, reps = gpe.pcg_solve_batched(probs, Vs, phis, "f64", tol=1e-10, max_iter=5000, precision="mixed",
+                                         use_graph=g)
+        assert st == 0
+        out[g] = (reps, [p.cpu().numpy() for p in phis])
+    for a, b in zip(out[0][0], out[1][0]):
+        assert a["iters"] == b["iters"] and a["E"] == b["E"]
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
