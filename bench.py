@@ -92,6 +92,33 @@ def applies_per_s(torch, plan, phi, V, reps, batched=False):
     return count / sec, sec / reps
 
 
+def applies_per_s_graph(torch, plan, phi, V, reps=1000):
+    """H_phi applies/s of a captured graph of `reps` applies (one field), replayed once; the output of
+    the replay is checked against an eager apply."""
+    out = torch.empty_like(phi)
+    ref = plan.apply_H(phi, V)  # also sizes the plan's scratch before capture
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(reps):
+                plan.apply_H(phi, V, out, stream=side)
+    torch.cuda.synchronize()
+    graph.replay()  # warm
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s = torch.cuda.current_stream()
+    e0.record(s)
+    graph.replay()
+    e1.record(s)
+    e1.synchronize()
+    if not torch.equal(out, ref):
+        raise RuntimeError("graph-replayed H apply differs from the eager apply")
+    return reps / (e0.elapsed_time(e1) / 1e3)
+
+
 def cpu_baseline(prob, V, phi0, iters, gpu_fp64_iters_total):
     """The FP64 oracle, as it stands, on the same workload for a bounded number of iterations."""
     from oracle import gpe_oracle as O
@@ -317,6 +344,8 @@ def main():
     bphi32 = phi32.unsqueeze(0).repeat(batch, 1, 1).contiguous()
     apb64, tb64 = applies_per_s(torch, plan64, bphi64, V, 20, batched=True)
     apb32, tb32 = applies_per_s(torch, plan32, bphi32, V32, 20, batched=True)
+    apg64 = applies_per_s_graph(torch, plan64, phi0, V)
+    apg32 = applies_per_s_graph(torch, plan32, phi32, V32)
 
     # per-kernel timings of the step's iteration (all eight starts), FP32 fields and FP64 fields
     log("[bench] kernel profile")
@@ -374,7 +403,8 @@ def main():
         "sweep_64": sweep,
         "other_configs": configs,
         "pcg_iters_per_s_step": {"mixed": max(it_mixed) / mean(t_mixed), "fp64": max(it_fp64) / mean(t_fp64)},
-        "h_applies_per_s": {"fp64": ap64, "fp32": ap32, "fp64_batch32": apb64, "fp32_batch32": apb32},
+        "h_applies_per_s": {"fp64": ap64, "fp32": ap32, "fp64_batch32": apb64, "fp32_batch32": apb32,
+                            "fp64_graph1000": apg64, "fp32_graph1000": apg32},
         "h_apply_batch32_hbm_gbs": {
             "fp64": 11 * 8 * 512 * 512 * batch / tb64 / 1e9, "fp32": 11 * 4 * 512 * 512 * batch / tb32 / 1e9},
         "final": {"E_mixed": [r["E"] for r in reps_mixed], "res_mixed": max(r["res_inf"] for r in reps_mixed),

@@ -153,3 +153,33 @@ def test_energy_grad(torch_gpu):
     assert abs(db - 0.5 * w * np.sum(np.abs(phi) ** 4)) < 1e-12 * abs(db)
     lz = O.inner(prob, phi, O.angular_momentum(prob, phi)).real
     assert abs(do + lz) < 1e-12 * max(1.0, abs(lz))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_apply_H_replayed_from_a_captured_graph(torch_gpu, dtype):
+    """The H apply captured into a graph (after an eager call sized the plan's scratch) and replayed
+    three times, with other eager applies and synchronisations between the replays: every replay
+    gives the eager result bit for bit (the graph holds kernel nodes only)."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, phi = _setup(2, (64, 128), (6.0, 8.0))
+    plan = gpe.Plan.from_problem(prob, dtype)
+    f, Vd = _to(torch, phi, dtype), _to(torch, V, dtype)
+    other = _to(torch, random_field(prob, 77, envelope=0.02), dtype)
+    ref = plan.apply_H(f, Vd)
+    out = torch.empty_like(f)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            plan.apply_H(f, Vd, out, stream=side)
+    torch.cuda.synchronize()
+    for k in range(3):
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {k}"
+        plan.apply_H(other, Vd)  # eager work between replays
+        torch.cuda.synchronize()
