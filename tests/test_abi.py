@@ -92,3 +92,30 @@ def test_default_options(gpe):
     assert o.method == 1 and o.precond == 3 and o.tol_res_inf == 1e-8
     o = gpe.default_opts(precond="kinetic", method="pg", precision="mixed")
     assert (o.precond, o.method, o.precision) == (1, 0, 1)
+
+
+def test_default_options_enable_graph_replay(gpe):
+    assert gpe.default_opts().use_graph == 1
+    assert gpe.default_opts(use_graph=0).use_graph == 0
+
+
+def test_invalid_nested_and_be_arguments_are_rejected_on_the_host(gpe):
+    """Argument checks of the nested-grid solve, the interpolation and the backward Euler solver run
+    before any device call."""
+    L = gpe.lib()
+    o = gpe.default_opts()
+    P = (gpe.Problem * 1)(gpe.make_problem(2, (64, 64), (8.0, 8.0), 10.0, 0.3))
+    ptrs = (ctypes.c_void_p * 8)(*([1] * 8))  # never dereferenced: validation fails first
+    rep = (gpe.PcgReport * 8)()
+    # no instances / no levels / bad coarse tolerance
+    assert L.gpe_pcg_solve_nested(0, 2, P, 0, ptrs, ptrs, ptrs, ctypes.byref(o), 1e-6, rep, None) == -1
+    assert L.gpe_pcg_solve_nested(1, 0, P, 0, ptrs, ptrs, ptrs, ctypes.byref(o), 1e-6, rep, None) == -1
+    assert L.gpe_pcg_solve_nested(1, 2, P, 0, ptrs, ptrs, ptrs, ctypes.byref(o), 0.0, rep, None) == -1
+    assert L.gpe_pcg_solve_nested(1, 2, P, 7, ptrs, ptrs, ptrs, ctypes.byref(o), 1e-6, rep, None) == -1
+    # the finest level would exceed 1024 points per axis (64 << 5 = 2048)
+    assert L.gpe_pcg_solve_nested(1, 6, P, 0, ptrs, ptrs, ptrs, ctypes.byref(o), 1e-6, rep, None) == -2
+    assert b"1024" in L.gpe_last_error()
+    # NULL plan / fields
+    assert L.gpe_prolong(None, None, None, None) == -1
+    inner = ctypes.c_int64()
+    assert L.gpe_be_solve(None, None, None, 0.1, 1, ctypes.byref(o), 1e-10, ctypes.byref(inner), None, None) == -1
