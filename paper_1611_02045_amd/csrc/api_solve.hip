@@ -551,6 +551,7 @@ int gpe_pcg_solve_nested(int count, int levels, const gpe_problem_t* coarsest, i
     }
     if (dtype != GPE_F64 && dtype != GPE_F32) { set_error("dtype must be GPE_F64 or GPE_F32"); return GPE_EINVAL; }
     if (!(tol_coarse > 0.0) || !std::isfinite(tol_coarse)) { set_error("tol_coarse must be positive"); return GPE_EINVAL; }
+    if (levels > 8) { set_error("at most 8 nested levels (grids of 8 to 1024 points per axis)"); return GPE_EUNSUPPORTED; }
     int st = validate_opts(opts);
     if (st != GPE_OK) return st;
     // level l: the coarsest problem with 2^l times the points per axis, same box

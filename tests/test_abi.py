@@ -115,6 +115,7 @@ def test_invalid_nested_and_be_arguments_are_rejected_on_the_host(gpe):
     # the finest level would exceed 1024 points per axis (64 << 5 = 2048)
     assert L.gpe_pcg_solve_nested(1, 6, P, 0, ptrs, ptrs, ptrs, ctypes.byref(o), 1e-6, rep, None) == -2
     assert b"1024" in L.gpe_last_error()
+    assert L.gpe_pcg_solve_nested(1, 40, P, 0, ptrs, ptrs, ptrs, ctypes.byref(o), 1e-6, rep, None) == -2
     # NULL plan / fields
     assert L.gpe_prolong(None, None, None, None) == -1
     inner = ctypes.c_int64()
