@@ -124,9 +124,7 @@ typedef struct gpe_pcg_opts {
     int32_t check_every;   /* iterations queued between convergence polls */
     int32_t record_history;/* nonzero: keep per-iteration scalars (see gpe_pcg_history) */
     int32_t use_graph;     /* nonzero: after the first chunk, replay the chunk of check_every
-                            * iterations as a captured HIP graph (needs an even check_every; used
-                            * by single solves and single-instance batches, whose one host thread
-                            * drives the solve) */
+                            * iterations as a captured HIP graph (needs an even check_every) */
 } gpe_pcg_opts_t;
 
 typedef struct gpe_pcg_report {

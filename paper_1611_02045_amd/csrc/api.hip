@@ -41,6 +41,11 @@ Geo make_geo(const gpe_problem_t& p) {
     return g;
 }
 
+std::mutex& capture_mutex() {
+    static std::mutex m;
+    return m;
+}
+
 hipError_t build_twiddles(const Geo& g, Twiddles& tw) {
     for (int a = 0; a < g.dim; ++a) {
         const int M = g.n[a];
@@ -56,6 +61,7 @@ hipError_t build_twiddles(const Geo& g, Twiddles& tw) {
         hipError_t e;
         if ((e = tw.t64[a].ensure(sizeof(double) * 2 * M)) != hipSuccess) return e;
         if ((e = tw.t32[a].ensure(sizeof(float) * 2 * M)) != hipSuccess) return e;
+        std::lock_guard<std::mutex> lock(capture_mutex());
         if ((e = hipMemcpy(tw.t64[a].ptr, t64.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice)) != hipSuccess)
             return e;
         if ((e = hipMemcpy(tw.t32[a].ptr, t32.data(), sizeof(float) * 2 * M, hipMemcpyHostToDevice)) != hipSuccess)
@@ -70,6 +76,7 @@ hipError_t reduce_init(Reduce& r, int instances, int slots, size_t part_doubles)
     const size_t cbytes = sizeof(unsigned int) * (size_t)instances * slots;
     if (cbytes > r.counters.bytes) {
         if ((e = r.counters.ensure(cbytes)) != hipSuccess) return e;
+        std::lock_guard<std::mutex> lock(capture_mutex());
         if ((e = hipMemset(r.counters.ptr, 0, r.counters.bytes)) != hipSuccess) return e;
         if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
     }
@@ -152,7 +159,10 @@ int gpe_plan_create(const gpe_problem_t* prob, int dtype, gpe_plan_t** out) {
 
 int gpe_plan_destroy(gpe_plan_t* plan) {
     if (!plan) return GPE_OK;
-    (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lock(capture_mutex());
+        (void)hipDeviceSynchronize();
+    }
     plan->release();
     delete plan;
     return GPE_OK;

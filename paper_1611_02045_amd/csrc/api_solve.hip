@@ -304,11 +304,14 @@ int run_concurrent(int n, hipStream_t s, F task) {
     std::vector<hipStream_t> ss(n, s);
     int created = 1;
     hipError_t e = hipEventRecord(ev, s);  // the inputs are ready on the caller's stream
-    for (int k = 1; k < n && e == hipSuccess; ++k) {
-        e = hipStreamCreateWithFlags(&ss[k], hipStreamNonBlocking);
-        if (e == hipSuccess) {
-            created = k + 1;
-            e = hipStreamWaitEvent(ss[k], ev, 0);
+    {
+        std::lock_guard<std::mutex> lock(capture_mutex());
+        for (int k = 1; k < n && e == hipSuccess; ++k) {
+            e = hipStreamCreateWithFlags(&ss[k], hipStreamNonBlocking);
+            if (e == hipSuccess) {
+                created = k + 1;
+                e = hipStreamWaitEvent(ss[k], ev, 0);
+            }
         }
     }
     std::vector<int> st(n, GPE_OK);
@@ -332,11 +335,12 @@ int run_concurrent(int n, hipStream_t s, F task) {
         run(0);
         for (auto& t : th) t.join();
     }
-    for (int k = 1; k < created; ++k) {
-        (void)hipStreamSynchronize(ss[k]);
-        (void)hipStreamDestroy(ss[k]);
+    for (int k = 1; k < created; ++k) (void)hipStreamSynchronize(ss[k]);
+    {
+        std::lock_guard<std::mutex> lock(capture_mutex());
+        for (int k = 1; k < created; ++k) (void)hipStreamDestroy(ss[k]);
+        (void)hipEventDestroy(ev);
     }
-    (void)hipEventDestroy(ev);
     HIPCHK(e);
     // a HIP or argument error first (the tasks' outputs are then unreliable), else the worst status
     // (per-instance reports stay valid for the others), with the message of the task that set it
@@ -528,10 +532,7 @@ int gpe_pcg_solve_batched(int count, const gpe_problem_t* probs, int dtype, void
         gV[i] = V[order[i]];
         gphi[i] = phi_inout[order[i]];
     }
-    // Graph capture runs only where a single host thread drives the solve: HIP refuses the
-    // set-up calls of other threads (allocation, tables) while one thread captures.
-    gpe_pcg_opts_t o = *opts;
-    if (G > 1 || (int)(first[1] - first[0]) > 1) o.use_graph = 0;
+    const gpe_pcg_opts_t& o = *opts;
     const int worst = run_concurrent(G, s, [&](int g, hipStream_t sg) {
         const size_t a = first[g];
         return solve_group_split((int)(first[g + 1] - a), gp.data() + a, in_f64, gV.data() + a, gphi.data() + a,

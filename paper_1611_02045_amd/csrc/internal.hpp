@@ -1,6 +1,7 @@
 // Internal host interfaces of libgpe (not part of the C ABI).
 #pragma once
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -9,12 +10,18 @@
 
 namespace gpe {
 
+// Serialises a graph capture with the calls that synchronise the device or use the legacy default
+// stream (allocation, frees, table uploads, counter resets): HIP refuses them while another host
+// thread captures.  Held for the whole capture, and around each such call.
+std::mutex& capture_mutex();
+
 // Device buffer owned by a plan; grows on demand (never during graph capture).
 struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
     hipError_t ensure(size_t need) {
         if (need <= bytes) return hipSuccess;
+        std::lock_guard<std::mutex> lock(capture_mutex());
         if (ptr) {
             hipError_t e = hipFree(ptr);
             if (e != hipSuccess) return e;
@@ -26,7 +33,10 @@ struct DevBuf {
         return e;
     }
     void release() {
-        if (ptr) (void)hipFree(ptr);
+        if (ptr) {
+            std::lock_guard<std::mutex> lock(capture_mutex());
+            (void)hipFree(ptr);
+        }
         ptr = nullptr;
         bytes = 0;
     }

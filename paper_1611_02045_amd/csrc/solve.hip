@@ -214,6 +214,7 @@ static hipError_t zero_cg_memory(IterFields<T>& f, int64_t BN, hipStream_t s) {
 struct PrivateStream {
     hipStream_t s = nullptr;
     hipError_t create_after(hipStream_t other) {
+        std::lock_guard<std::mutex> lock(capture_mutex());
         hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
         if (e != hipSuccess) {
             s = nullptr;
@@ -229,18 +230,20 @@ struct PrivateStream {
     ~PrivateStream() {
         if (s) {
             (void)hipStreamSynchronize(s);
+            std::lock_guard<std::mutex> lock(capture_mutex());
             (void)hipStreamDestroy(s);
         }
     }
 };
 
-// An instantiated graph captured from work queued on one stream (thread-local capture mode: other
-// host threads may allocate or launch meanwhile).  Captures only kernel launches: no memory-set or
-// copy nodes.
+// An instantiated graph captured from work queued on one stream, under capture_mutex (other host
+// threads may launch meanwhile, but not allocate or touch the legacy stream).  Captures only kernel
+// launches: no memory-set or copy nodes.
 struct GraphExec {
     hipGraphExec_t exec = nullptr;
     template <class F>
     hipError_t capture(hipStream_t s, F enqueue) {
+        std::lock_guard<std::mutex> lock(capture_mutex());
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
         hipError_t qe = enqueue();
