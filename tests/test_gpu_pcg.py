@@ -237,8 +237,8 @@ def test_graph_replay_matches_eager_launches(torch_gpu, key, precision):
 
 
 def test_graph_option_batched_matches_eager(torch_gpu):
-    """The batched solve (two parts on two streams and threads, which launch eagerly whatever the
-    option) gives identical per-instance results with the graph option on and off."""
+    """The batched solve (two parts on two streams and threads, each capturing and replaying its own
+    graph) gives identical per-instance results with the graph option on and off."""
     from paper_1611_02045_amd import gpe
     torch = torch_gpu
     probs, Vs, starts = [], [], []
