@@ -98,6 +98,17 @@ int gpe_apply_H_batched(gpe_plan_t* plan, int count, const void* phi, const void
 int gpe_precond(gpe_plan_t* plan, int kind, const void* phi, const void* V, double alpha,
                 const void* r, void* Pr, void* stream);
 
+/* Tile measurement for the plan's grid and dtype at a batch of `count` fields per launch: for each
+ * axis, the directional pass (forward transform, multiplier, inverse transform) is timed for
+ * every valid number of lines per workgroup and the fastest is recorded, process-wide, for every
+ * later operator launch (H apply, energy, preconditioners) on that grid, dtype and batch size.
+ * The solver's own passes keep their rule: they absorb one partial row per producer workgroup,
+ * and the smaller workgroups an operator pass prefers made them slower.  tiles: host, 3 ints,
+ * the chosen lines per workgroup per axis (0 for absent axes); us: host, 3 doubles, the time per
+ * pass of the choice in microseconds; both nullable.  Uses the plan's scratch; must not run
+ * concurrently with operator calls on the same grid.  Synchronises. */
+int gpe_autotune(gpe_plan_t* plan, int count, int* tiles, double* us, void* stream);
+
 /* Interpolation onto the grid with twice the points per axis and the same box: the step between
  * the nested grids M_p -> M_{p+1} of the initial-data example of Section 6.2.  Per axis, the
  * trigonometric interpolant of the Section 3 discretisation, with the Nyquist coefficient split

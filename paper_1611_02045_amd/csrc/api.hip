@@ -2,7 +2,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -44,6 +46,25 @@ Geo make_geo(const gpe_problem_t& p) {
 std::mutex& capture_mutex() {
     static std::mutex m;
     return m;
+}
+
+namespace {
+using TileKey = std::tuple<int, int, int, int, int, int, int>;  // dim, n0, n1, n2, axis, point bytes, batch
+std::mutex g_tiles_mutex;
+std::map<TileKey, int> g_tiles;
+TileKey tile_key(const Geo& g, int AX, int cb, int B) { return TileKey{g.dim, g.n[0], g.n[1], g.n[2], AX, cb, B}; }
+}  // namespace
+
+int tuned_lines(const Geo& g, int AX, int complex_bytes, int B) {
+    std::lock_guard<std::mutex> lock(g_tiles_mutex);
+    if (g_tiles.empty()) return 0;
+    const auto it = g_tiles.find(tile_key(g, AX, complex_bytes, B));
+    return it == g_tiles.end() ? 0 : it->second;
+}
+
+void record_tuned_lines(const Geo& g, int AX, int complex_bytes, int B, int C) {
+    std::lock_guard<std::mutex> lock(g_tiles_mutex);
+    g_tiles[tile_key(g, AX, complex_bytes, B)] = C;
 }
 
 hipError_t build_twiddles(const Geo& g, Twiddles& tw) {
@@ -239,6 +260,25 @@ int gpe_precond(gpe_plan_t* plan, int kind, const void* phi, const void* V, doub
     const size_t cb = plan->f64() ? 16 : 8;
     HIPCHK(plan->tmp.ensure(cb * (size_t)plan->g.N));
     HIPCHK(op_precond(plan->g, plan->f64(), plan->tw, kind, phi, V, alpha_dev, plan->prob.beta, r, Pr, plan->tmp.ptr, s));
+    return GPE_OK;
+}
+
+int gpe_autotune(gpe_plan_t* plan, int count, int* tiles, double* us, void* stream) {
+    NEEDPTR(plan, "plan");
+    if (count < 1) { set_error("count must be >= 1"); return GPE_EINVAL; }
+    const size_t cb = plan->f64() ? 16 : 8;
+    const size_t bytes = cb * (size_t)plan->g.N * count;
+    HIPCHK(plan->tmp.ensure(2 * bytes));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemsetAsync(plan->tmp.ptr, 0, 2 * bytes, s));
+    int t[3] = {0, 0, 0};
+    double u[3] = {0.0, 0.0, 0.0};
+    HIPCHK(op_autotune(plan->g, plan->f64(), count, plan->tw, plan->tmp.ptr, (char*)plan->tmp.ptr + bytes, s, t, u));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int a = 0; a < 3; ++a) {
+        if (tiles) tiles[a] = t[a];
+        if (us) us[a] = u[a];
+    }
     return GPE_OK;
 }
 

@@ -75,6 +75,11 @@ hipError_t op_rotation(const Geo& g, bool f64, const Twiddles& tw, const void* f
 // 2^dim N points).  tmp: at least 2N (2-D) or 4N (3-D) complex values; unused in 1-D.
 hipError_t op_prolong(const Geo& g, bool f64, const Twiddles& tw, const void* in, void* out, void* tmp, hipStream_t s);
 
+// Tile measurement of the directional passes over B fields of the grid g (f, out: B*N complex
+// scratch values each); records the fastest lines per workgroup per axis (tiles, us: per axis).
+hipError_t op_autotune(const Geo& g, bool f64, int B, const Twiddles& tw, void* f, void* out, hipStream_t s,
+                       int tiles[3], double us[3]);
+
 // Energy parts of one field: dst (device, 4 doubles) <- {kinetic, potential, interaction, rotation}.
 hipError_t op_energy(const Geo& g, bool f64, const Twiddles& tw, const void* phi, const void* V,
                      double beta, double omega, Reduce& red, double* dst, hipStream_t s);

@@ -57,7 +57,22 @@ inline size_t pass_lds_bytes_cb(int cb, int M, int C, int threads, int K, int ax
 // the thread and LDS budgets and by n_x.  When the whole launch would have few workgroups (small
 // single grids) the groups are made smaller so that every CU gets work: these launches are bound
 // by latency, not bandwidth.
-inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes, int B = 1) {
+// Lines per workgroup chosen by measurement (gpe_autotune) for a grid, axis, point size and batch
+// size, or 0 when none was recorded; recording replaces the rule below for every later launch.
+int tuned_lines(const Geo& g, int AX, int complex_bytes, int B);
+void record_tuned_lines(const Geo& g, int AX, int complex_bytes, int B, int C);
+
+// Whether C lines per workgroup is a valid tile for a pass along AX (whole lines, at most 256
+// threads, C dividing the lines of a field, strided groups within n_x, LDS within budget).
+inline bool valid_lines(const Geo& g, int AX, int complex_bytes, int C) {
+    const int TPL = g.n[AX] / 8;
+    if (C < 1 || (C & (C - 1)) != 0 || C * TPL > 256) return false;
+    if (lines_per_field(g, AX) % C != 0) return false;
+    if (AX != 0 && C > g.n[0]) return false;
+    return pass_lds_bytes_cb(complex_bytes, g.n[AX], C, C * TPL, 32, AX) <= kPassLdsBudget;
+}
+
+inline int pass_lines_rule(const Geo& g, int AX, int complex_bytes, int B) {
     const int TPL = g.n[AX] / 8;
     const int64_t lpf = lines_per_field(g, AX);
     const int64_t lines = lpf * (int64_t)B;
@@ -81,16 +96,26 @@ inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes, int B =
     return C;
 }
 
-inline int pass_blocks_per_field(const Geo& g, int AX, int complex_bytes, int B = 1) {
-    return (int)(lines_per_field(g, AX) / pass_lines_per_block(g, AX, complex_bytes, B));
+// Lines per workgroup of a launch: operator passes take a measured tile when one was recorded;
+// solver passes (which absorb their producers' partial rows, one per workgroup) always take the
+// rule: tiles measured on the operator pass favour more, smaller workgroups, which made the
+// solver's passes up to 30% slower.
+inline int pass_lines_per_block(const Geo& g, int AX, int complex_bytes, int B, bool solver) {
+    if (!solver)
+        if (const int t = tuned_lines(g, AX, complex_bytes, B)) return t;
+    return pass_lines_rule(g, AX, complex_bytes, B);
+}
+
+inline int pass_blocks_per_field(const Geo& g, int AX, int complex_bytes, int B, bool solver) {
+    return (int)(lines_per_field(g, AX) / pass_lines_per_block(g, AX, complex_bytes, B, solver));
 }
 
 // Launch one pass over B instances.  `pr` receives nb (blocks per instance) if the Op reduces.
 template <typename T, int AX, class Op>
 hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partials pr, hipStream_t s,
-                       const LaunchEvents* ev = nullptr) {
+                       const LaunchEvents* ev = nullptr, int C_force = 0) {
     const int cb = (int)sizeof(C2<T>);
-    const int C = pass_lines_per_block(g, AX, cb, B);
+    const int C = C_force > 0 ? C_force : pass_lines_per_block(g, AX, cb, B, Op::SCALARS);
     const int TPL = g.n[AX] / 8;
     const int threads = C * TPL;
     const int nb = (int)(lines_per_field(g, AX) / C);

@@ -221,6 +221,65 @@ hipError_t op_prolong(const Geo& g, bool f64, const Twiddles& tw, const void* in
 }
 
 // ---------------------------------------------------------------------------------------------
+// Tile measurement: for each axis, the directional pass (forward transform, kinetic multiplier,
+// inverse transform, store) over B fields is timed for every valid number of lines per workgroup,
+// and the fastest is recorded for the grid, point size and batch size.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int AX>
+static hipError_t tune_axis(const Geo& g, int B, const Twiddles& tw, const C2<T>* f, C2<T>* out, hipStream_t s,
+                            int& best_C, double& best_us) {
+    const int cb = (int)sizeof(C2<T>);
+    const int TPL = g.n[AX] / 8;
+    OpApply<T, AX> op{f, nullptr, out, nullptr, 0.0, 0.0, 0, 0};
+    Partials none{nullptr, 0, 0, 0};
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+    best_C = 0;
+    best_us = 0.0;
+    // whole waves where the grid allows it (a partial wave idles lanes)
+    int Cmin = 1;
+    while (Cmin * TPL < 64 && valid_lines(g, AX, cb, 2 * Cmin)) Cmin *= 2;
+    for (int C = Cmin; C * TPL <= 256 && e == hipSuccess; C *= 2) {
+        if (!valid_lines(g, AX, cb, C)) continue;
+        constexpr int kWarm = 2, kReps = 10;
+        for (int r = 0; r < kWarm && e == hipSuccess; ++r) e = launch_pass<T, AX>(g, B, tw.get(AX, sizeof(T) == 8), op, none, s, nullptr, C);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch_pass<T, AX>(g, B, tw.get(AX, sizeof(T) == 8), op, none, s, nullptr, C);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / kReps;
+        if (e == hipSuccess && (best_C == 0 || us < best_us)) {
+            best_C = C;
+            best_us = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e == hipSuccess && best_C > 0) record_tuned_lines(g, AX, cb, B, best_C);
+    return e;
+}
+
+template <typename T>
+static hipError_t autotune_t(const Geo& g, int B, const Twiddles& tw, void* f, void* out, hipStream_t s, int tiles[3],
+                             double us[3]) {
+    const C2<T>* F = (const C2<T>*)f;
+    C2<T>* O = (C2<T>*)out;
+    hipError_t e = tune_axis<T, 0>(g, B, tw, F, O, s, tiles[0], us[0]);
+    if (e == hipSuccess && g.dim > 1) e = tune_axis<T, 1>(g, B, tw, F, O, s, tiles[1], us[1]);
+    if (e == hipSuccess && g.dim > 2) e = tune_axis<T, 2>(g, B, tw, F, O, s, tiles[2], us[2]);
+    return e;
+}
+
+hipError_t op_autotune(const Geo& g, bool f64, int B, const Twiddles& tw, void* f, void* out, hipStream_t s,
+                       int tiles[3], double us[3]) {
+    return f64 ? autotune_t<double>(g, B, tw, f, out, s, tiles, us) : autotune_t<float>(g, B, tw, f, out, s, tiles, us);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Energy: forward transforms only; Parseval turns <phi, F^{-1} sigma F phi> into
 // (1/M) sum sigma |F phi|^2 per line.  Sums: {kinetic, rotation, potential, quartic}.
 // ---------------------------------------------------------------------------------------------
@@ -297,7 +356,7 @@ static hipError_t energy_t(const Geo& g, const Twiddles& tw, const void* phi, co
     hipError_t e;
     for (int ax = 0; ax < g.dim; ++ax) {
         Partials pr{parts + off, 0, 0, 0};
-        const int nb = pass_blocks_per_field(g, ax, cb);
+        const int nb = pass_blocks_per_field(g, ax, cb, 1, false);
         if (ax == 0) e = launch_pass<T, 0>(g, 1, tw.get(0, f64), OpEnergy<T, 0>{P, (const T*)V, omega}, pr, s);
         else if (ax == 1) e = launch_pass<T, 1>(g, 1, tw.get(1, f64), OpEnergy<T, 1>{P, (const T*)V, omega}, pr, s);
         else e = launch_pass<T, 2>(g, 1, tw.get(2, f64), OpEnergy<T, 2>{P, (const T*)V, omega}, pr, s);

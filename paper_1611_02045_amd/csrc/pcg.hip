@@ -843,7 +843,7 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     Scal* S_dir = c.S + 2 * c.B;
     hipError_t e;
     auto region = [&](int r, int ax) {
-        const int nb = pass_blocks_per_field(g, ax, cb, c.B);
+        const int nb = pass_blocks_per_field(g, ax, cb, c.B, true);
         return Partials{c.parts + (size_t)r * c.region_doubles, nb, nb, 0};
     };
     // the view a consumer absorbs: the region itself, or its one-row collapse for many rows
@@ -867,9 +867,9 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     // The direction passes (x, y, z) share one region of B-sum rows, each pass at its own offset
     // within an instance's rows; the step absorbs them at the next iteration's start, through their
     // one-row collapse when they are many.
-    const int nbx = pass_blocks_per_field(g, 0, cb, c.B);
-    const int nby = g.dim >= 2 ? pass_blocks_per_field(g, 1, cb, c.B) : 0;
-    const int nbz = g.dim >= 3 ? pass_blocks_per_field(g, 2, cb, c.B) : 0;
+    const int nbx = pass_blocks_per_field(g, 0, cb, c.B, true);
+    const int nby = g.dim >= 2 ? pass_blocks_per_field(g, 1, cb, c.B, true) : 0;
+    const int nbz = g.dim >= 3 ? pass_blocks_per_field(g, 2, cb, c.B, true) : 0;
     const int nbB = nbx + nby + nbz;
     double* const partsB = c.parts + (size_t)R_B * c.region_doubles;
     const Partials pb0{partsB, nbx, nbB, 0}, pb1{partsB, nby, nbB, nbx}, pb2{partsB, nbz, nbB, nbx + nby};

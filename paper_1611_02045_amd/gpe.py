@@ -68,6 +68,7 @@ SIGNATURES = {
     "gpe_pcg_solve_batched": (_I, [_I, ctypes.POINTER(Problem), _I, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                    ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
     "gpe_prolong": (_I, [_VP, _VP, _VP, _VP]),
+    "gpe_autotune": (_I, [_VP, _I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_D), _VP]),
     "gpe_be_solve": (_I, [_VP, _VP, _VP, _D, _I, ctypes.POINTER(PcgOpts), _D, ctypes.POINTER(ctypes.c_int64),
                           ctypes.POINTER(PcgReport), _VP]),
     "gpe_pcg_solve_nested": (_I, [_I, _I, ctypes.POINTER(Problem), _I, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
@@ -219,6 +220,14 @@ class Plan:
                                          self._field(V, "V", False), self._field(out, "out", batch=count),
                                          _stream(stream)))
         return out
+
+    def autotune(self, count: int = 1, stream=None):
+        """Measure and record the fastest lines per workgroup of each axis's pass for batches of
+        `count` fields: returns ([tile per axis], [microseconds per pass])."""
+        t = (ctypes.c_int * 3)()
+        u = (ctypes.c_double * 3)()
+        _check(lib().gpe_autotune(self._h, int(count), t, u, _stream(stream)))
+        return list(t)[: len(self.shape)], list(u)[: len(self.shape)]
 
     def prolong(self, phi, out=None, stream=None):
         """phi interpolated onto the grid with twice the points per axis (same box)."""

@@ -120,3 +120,8 @@ def test_invalid_nested_and_be_arguments_are_rejected_on_the_host(gpe):
     assert L.gpe_prolong(None, None, None, None) == -1
     inner = ctypes.c_int64()
     assert L.gpe_be_solve(None, None, None, 0.1, 1, ctypes.byref(o), 1e-10, ctypes.byref(inner), None, None) == -1
+
+
+def test_autotune_rejects_bad_arguments(gpe):
+    L = gpe.lib()
+    assert L.gpe_autotune(None, 1, None, None, None) == -1

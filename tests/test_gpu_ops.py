@@ -183,3 +183,25 @@ def test_apply_H_replayed_from_a_captured_graph(torch_gpu, dtype):
         assert torch.equal(out, ref), f"replay {k}"
         plan.apply_H(other, Vd)  # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_autotuned_tiles_keep_parity(torch_gpu, dtype):
+    """After tile measurement on a grid, every pass launches with the recorded tiles: the H apply
+    and a full solve still match the oracle."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, phi = _setup(2, (128, 64), (8.0, 6.0))
+    plan = gpe.Plan.from_problem(prob, dtype)
+    tiles, us = plan.autotune(1)
+    print(f"tiles {tiles} us {us}", flush=True)
+    assert all(t >= 1 for t in tiles) and all(u > 0.0 for u in us)
+    out = plan.apply_H(_to(torch, phi, dtype), _to(torch, V, dtype)).cpu().numpy()
+    ref = O.hamiltonian(prob, V, phi)
+    assert _relerr(out, ref) < TOL[dtype]
+    if dtype == "f64":
+        ph = _to(torch, phi, dtype)
+        rep = plan.pcg_solve(_to(torch, V, dtype), ph, tol=1e-9, max_iter=5000)
+        assert rep["status"] == 0
+        E = O.energy(prob, V, ph.cpu().numpy())
+        assert abs(E - rep["E"]) < 1e-12 * abs(E)
