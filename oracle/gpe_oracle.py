@@ -293,6 +293,62 @@ def theta_derivatives(prob, V, phi, phat, lam: float):
     return d1, d2
 
 
+def energy_slope(prob, V, phi, phat, theta: float) -> float:
+    """dE/dtheta of theta -> E(u), u = cos(theta) phi + sin(theta) phat, by the chain rule on the
+    Section 2 gradient: E'(u)[u'] = 2 Re<H_u u, u'>, u' = -sin(theta) phi + cos(theta) phat."""
+    c, s = math.cos(theta), math.sin(theta)
+    u = c * phi + s * phat
+    du = -s * phi + c * phat
+    return 2.0 * inner(prob, hamiltonian(prob, V, u), du).real
+
+
+# Samples of the period [0, pi) that locate the global minimiser of the full line search.
+FULL_SEARCH_SAMPLES = 64
+# Sufficient-decrease constant of the Armijo test (the paper names the test, not the constant;
+# reading: the customary 1e-4).
+ARMIJO_C1 = 1e-4
+
+
+def theta_full(prob, V, phi, phat, Lphi, Lphat, samples: int = FULL_SEARCH_SAMPLES) -> float:
+    """The full line search of Section 5.1: theta = argmin E(cos theta phi + sin theta phat).
+    E along the great circle has period pi (u -> -u leaves E unchanged), so the minimiser is
+    sought in [0, pi).  Readings: the global minimiser is taken; it is located on `samples` equally
+    spaced angles (the energy change of each, see energy_change), then refined to a zero of the
+    slope (energy_slope) bracketed between the best angle and the neighbour towards which the
+    energy falls, by Brent's method to a few ulps.  The result is reduced into [0, pi)."""
+    from scipy.optimize import brentq
+
+    step = math.pi / samples
+    vals = [energy_change(prob, phi, phat, Lphi, Lphat, k * step) for k in range(samples)]
+    k = int(np.argmin(vals))
+    t0 = k * step
+    g0 = energy_slope(prob, V, phi, phat, t0)
+    lo, hi = (t0, t0 + step) if g0 < 0.0 else (t0 - step, t0)
+    glo, ghi = energy_slope(prob, V, phi, phat, lo), energy_slope(prob, V, phi, phat, hi)
+    if g0 == 0.0 or not (glo < 0.0 < ghi):
+        t = t0
+    else:
+        t = brentq(lambda x: energy_slope(prob, V, phi, phat, x), lo, hi, xtol=1e-300, rtol=4 * EPS64,
+                   maxiter=200)
+    return t % math.pi
+
+
+def trial_ladder(prob, phi, phat, Lphi, Lphat, theta: float, d1: float, max_halvings: int,
+                 armijo: bool = False):
+    """Step control of Section 5.1: the trials theta, theta/2, theta/4, ... (at most max_halvings
+    halvings); the first whose energy change is negative is accepted (with armijo=True, the first
+    that also satisfies E(t) - E(0) <= ARMIJO_C1 t E'(0), E'(0) = d1).  Returns (t, halvings), or
+    (None, max_halvings) when no trial passes."""
+    for j in range(max_halvings + 1):
+        t = theta * 0.5 ** j
+        if not t > 0.0:
+            continue
+        dE = energy_change(prob, phi, phat, Lphi, Lphat, t)
+        if dE < 0.0 and (not armijo or dE <= ARMIJO_C1 * t * d1):
+            return t, j
+    return None, max_halvings
+
+
 # ----------------------------------------------------------------------------------------------
 # PG / PCG on the sphere (Algorithms 1 and 2, Sections 5.1-5.3)
 # ----------------------------------------------------------------------------------------------
@@ -312,7 +368,8 @@ class SolveResult:
 
 def pcg(prob, V, phi0, *, method: str = "pcg", precond: str = "combined", tol_res: float = 1e-8,
         tol_energy: float = 0.0, max_iter: int = 10_000, theta_default: float = 0.1,
-        max_halvings: int = 30, beta_rule: str = "pr", record: bool = False) -> SolveResult:
+        max_halvings: int = 30, beta_rule: str = "pr", line_search: str = "heuristic",
+        record: bool = False) -> SolveResult:
     """Projected preconditioned gradient (method="pg", Algorithm 1) or conjugate gradient
     (method="pcg", Algorithm 2) minimisation of E on the unit sphere, with the step control of
     Sections 5.1-5.2 and the residual stopping rule of Section 5.3.
@@ -326,12 +383,18 @@ def pcg(prob, V, phi0, *, method: str = "pcg", precond: str = "combined", tol_re
       * trial step theta_opt = -E'(0)/E''(0) when E''(0) > 0, else theta_default; clamped to
         (0, pi/2]; halved until the energy decreases (at most max_halvings times, after which the
         run stops with status "linesearch");
+      * line_search="armijo" accepts a trial only when E(theta) - E(0) <= ARMIJO_C1 theta E'(0)
+        (the Armijo test the section names as an alternative), halving as above;
+        line_search="full" takes theta_full (the full line search of the section), accepted
+        when it decreases the energy, else the run stops with status "linesearch";
       * phi is renormalised after every step;
       * stop when ||r_n||_inf <= tol_res at the top of iteration n (or, when tol_energy > 0,
         when |E_{n+1} - E_n| <= tol_energy).
     """
     if method not in ("pg", "pcg"):
         raise ValueError("method must be 'pg' or 'pcg'")
+    if line_search not in ("heuristic", "armijo", "full"):
+        raise ValueError("line_search must be 'heuristic', 'armijo' or 'full'")
     phi = np.array(phi0, dtype=np.complex128, copy=True)
     phi /= norm(prob, phi)
     r_prev = p_prev = None
@@ -384,13 +447,15 @@ def pcg(prob, V, phi0, *, method: str = "pcg", precond: str = "combined", tol_re
         theta = min(max(theta, 0.0), 0.5 * math.pi)
         Lphi = linear_part(prob, V, phi)
         Lphat = linear_part(prob, V, phat)
-        accepted = None
-        for j in range(max_halvings + 1):
-            t = theta * 0.5 ** j
-            if t > 0.0 and energy_change(prob, phi, phat, Lphi, Lphat, t) < 0.0:
-                accepted = t
+        j = 0
+        if line_search == "full":
+            t = theta_full(prob, V, phi, phat, Lphi, Lphat)
+            accepted = t if energy_change(prob, phi, phat, Lphi, Lphat, t) < 0.0 else None
+        else:
+            accepted, j = trial_ladder(prob, phi, phat, Lphi, Lphat, theta, d1, max_halvings,
+                                       armijo=line_search == "armijo")
+            if accepted is not None:
                 halvings += j
-                break
         if accepted is None:
             status = "linesearch"
             break

@@ -187,6 +187,100 @@ def test_energy_change_equals_plain_difference():
         assert abs(O.energy_change(prob, phi, phat, Lphi, Lphat, t) - plain) < 1e-10 * (1 + abs(plain))
 
 
+def _circle_case(seed, beta, omega):
+    prob = Problem(2, (32, 32), (6.0, 6.0), beta, omega)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, seed, envelope=0.15)
+    phi = phi / O.norm(prob, phi)
+    q = O.project(prob, phi, random_field(prob, seed + 1, envelope=0.15))
+    phat = q / O.norm(prob, q)
+    return prob, V, phi, phat, O.linear_part(prob, V, phi), O.linear_part(prob, V, phat)
+
+
+def test_full_line_search_without_interaction_is_rayleigh_ritz():
+    """beta = 0: E(cos t phi + sin t phat) is the quadratic form of the 2x2 matrix
+    [[E(phi), b], [b, E(phat)]] with b = E(pi/4) - (E(phi) + E(phat))/2 (plain energies), so the
+    full line search must land on its lowest eigenvalue and eigenvector (numpy eigh)."""
+    prob, V, phi, phat, Lphi, Lphat = _circle_case(31, 0.0, 0.7)
+    a = O.energy(prob, V, phi)
+    c = O.energy(prob, V, phat)
+    b = O.energy_along(prob, V, phi, phat, math.pi / 4) - 0.5 * (a + c)
+    w, v = np.linalg.eigh(np.array([[a, b], [b, c]]))
+    t = O.theta_full(prob, V, phi, phat, Lphi, Lphat)
+    assert 0.0 <= t < math.pi
+    assert abs(O.energy_along(prob, V, phi, phat, t) - w[0]) < 1e-12 * abs(w[0])
+    # the minimiser is the eigenvector's angle (up to sign)
+    assert abs(math.sin(t - math.atan2(v[1, 0], v[0, 0]))) < 1e-7
+
+
+@pytest.mark.parametrize("seed,beta,omega", [(40, 400.0, 0.6), (44, 1500.0, 0.9), (48, 50.0, 0.0)])
+def test_full_line_search_is_the_global_minimiser(seed, beta, omega):
+    """Against plain energies only: no angle of a 4096-point scan of [0, pi) lies below
+    E(theta_full), the central difference of E at theta_full vanishes to its truncation error,
+    and E rises on both sides."""
+    prob, V, phi, phat, Lphi, Lphat = _circle_case(seed, beta, omega)
+    t = O.theta_full(prob, V, phi, phat, Lphi, Lphat)
+    Et = O.energy_along(prob, V, phi, phat, t)
+    scan = [O.energy_along(prob, V, phi, phat, x) for x in np.linspace(0.0, math.pi, 4096, endpoint=False)]
+    assert min(scan) >= Et - 1e-13 * abs(Et)
+    h = 1e-4
+    Ep, Em = O.energy_along(prob, V, phi, phat, t + h), O.energy_along(prob, V, phi, phat, t - h)
+    curv = (Ep - 2 * Et + Em) / h ** 2
+    assert curv > 0.0
+    assert abs((Ep - Em) / (2 * h)) < 1e-6 * (1.0 + curv)
+    # the slope formula itself, against central differences away from the minimiser
+    for x in (0.1, 0.9, 2.3):
+        fd = (O.energy_along(prob, V, phi, phat, x + h) - O.energy_along(prob, V, phi, phat, x - h)) / (2 * h)
+        assert abs(O.energy_slope(prob, V, phi, phat, x) - fd) < 1e-6 * (1.0 + abs(fd))
+
+
+def test_armijo_rejects_a_trial_the_decrease_test_accepts():
+    """A trial just inside the zero crossing of E(t) - E(0) decreases the energy but by less than
+    ARMIJO_C1 t E'(0): the decrease test accepts it at once, the Armijo test halves it.  The
+    accepted Armijo step is checked with plain energies and a finite-difference E'(0)."""
+    from scipy.optimize import brentq
+
+    prob, V, phi, phat, Lphi, Lphat = _circle_case(52, 300.0, 0.5)
+    if O.energy_slope(prob, V, phi, phat, 0.0) > 0.0:
+        phat = -phat
+        Lphat = -Lphat
+    E0 = O.energy(prob, V, phi)
+    h = 1e-5
+    d1 = (O.energy_along(prob, V, phi, phat, h) - O.energy_along(prob, V, phi, phat, -h)) / (2 * h)
+    assert d1 < 0.0
+    # first zero of E(t) - E(0) beyond the minimiser along the circle
+    tmin = O.theta_full(prob, V, phi, phat, Lphi, Lphat)
+    t0 = brentq(lambda x: O.energy_along(prob, V, phi, phat, x) - E0, tmin, tmin + 1.5, xtol=1e-14)
+    theta = t0 * (1.0 - 1e-6)
+    dE = O.energy_along(prob, V, phi, phat, theta) - E0
+    assert O.ARMIJO_C1 * theta * d1 < dE < 0.0
+    t_dec, j_dec = O.trial_ladder(prob, phi, phat, Lphi, Lphat, theta, d1, 30, armijo=False)
+    t_arm, j_arm = O.trial_ladder(prob, phi, phat, Lphi, Lphat, theta, d1, 30, armijo=True)
+    assert (t_dec, j_dec) == (theta, 0)
+    assert j_arm >= 1 and t_arm == theta * 0.5 ** j_arm
+    assert O.energy_along(prob, V, phi, phat, t_arm) - E0 <= O.ARMIJO_C1 * t_arm * d1
+    prev = 2.0 * t_arm
+    assert O.energy_along(prob, V, phi, phat, prev) - E0 > O.ARMIJO_C1 * prev * d1
+
+
+@pytest.mark.parametrize("line_search", ["heuristic", "armijo", "full"])
+@pytest.mark.parametrize("beta_rule", ["pr", "fr"])
+def test_step_rules_reach_the_same_ground_state(line_search, beta_rule):
+    """Every step control and CG coefficient ends at the non-rotating ground state: lambda is the
+    lowest eigenvalue of the frozen Hamiltonian L + beta |phi|^2 (dense numpy eigh) and phi its
+    eigenvector."""
+    prob = Problem(1, (128,), (12.0,), 100.0, 0.0)
+    V = harmonic_potential(prob)
+    r = O.pcg(prob, V, noisy_gaussian_1d(prob), tol_res=1e-10, max_iter=3000, line_search=line_search,
+              beta_rule=beta_rule)
+    assert r.status == "converged"
+    H = O.dense_operator(prob, lambda f: O.linear_part(prob, V, f) + prob.beta * np.abs(r.phi) ** 2 * f)
+    w, v = np.linalg.eigh(0.5 * (H + H.conj().T))
+    assert abs(r.lam - w[0]) < 1e-9
+    overlap = abs(np.vdot(v[:, 0], r.phi.ravel())) / np.linalg.norm(r.phi)
+    assert overlap > 1.0 - 1e-9
+
+
 # ----------------------------------------------------------------------------------------------
 # Preconditioners
 # ----------------------------------------------------------------------------------------------
