@@ -136,6 +136,13 @@ typedef struct gpe_pcg_opts {
     int32_t record_history;/* nonzero: keep per-iteration scalars (see gpe_pcg_history) */
     int32_t use_graph;     /* nonzero: after the first chunk, replay the chunk of check_every
                             * iterations as a captured HIP graph (needs an even check_every) */
+    int32_t line_search;   /* step control of Section 5.1: 0 = the trials theta_opt, theta_opt/2, ...
+                            * (at most max_halvings halvings), the first that lowers E accepted;
+                            * 1 = the same trials under the Armijo test
+                            * E(t) - E(0) <= 1e-4 t E'(0); 2 = full line search: the global
+                            * minimiser over [0, pi) of E(cos t phi + sin t phat), accepted when it
+                            * lowers E (one evaluation of the exact energy polynomial per angle,
+                            * no extra pass over the fields) */
 } gpe_pcg_opts_t;
 
 typedef struct gpe_pcg_report {
@@ -152,7 +159,8 @@ typedef struct gpe_pcg_report {
 } gpe_pcg_report_t;
 
 /* Fill *opts with defaults: PCG, P_C, tol 1e-8, 20000 iterations, FP64, Polak-Ribiere,
- * switch_res 1e-6, theta_default 0.1, 30 halvings, refresh every 50, poll every 16, graph replay on. */
+ * switch_res 1e-6, theta_default 0.1, 30 halvings, refresh every 50, poll every 16, graph replay on,
+ * the decrease-test line search. */
 void gpe_pcg_opts_default(gpe_pcg_opts_t* opts);
 
 /* Ground state by PG / PCG on the unit sphere (Algorithms 1-2 with the step control of

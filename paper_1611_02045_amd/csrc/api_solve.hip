@@ -399,6 +399,7 @@ void gpe_pcg_opts_default(gpe_pcg_opts_t* o) {
     o->check_every = 16;
     o->record_history = 0;
     o->use_graph = 1;
+    o->line_search = 0;
 }
 
 int gpe_pcg_solve(gpe_plan_t* plan, const void* V, void* phi_inout, const gpe_pcg_opts_t* opts,

@@ -94,6 +94,7 @@ struct alignas(16) Scal {
     int64_t best_n;
     double switch_res;
     int32_t stall_window, has_step;   // has_step: a retraction step is pending (applied by phase A)
+    int32_t line_search, pad0;        // 0 decrease test, 1 Armijo test, 2 full line search
     // history
     double* hist;      // device ring of rows of 8 doubles, nullable
     int64_t hist_cap;

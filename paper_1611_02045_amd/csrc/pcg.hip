@@ -165,8 +165,72 @@ __device__ __forceinline__ double delta_energy(double c, double s, double a, dou
     return quad + 0.5 * beta * quart;
 }
 
+// Slope and curvature of delta_energy in t.  In double angles (C2, S2 = cos 2t, sin 2t; C4, S4 =
+// cos 4t, sin 4t): s^2 = (1 - C2)/2, 2cs = S2, 4c^2s^2 = (1 - C4)/2, 4cs^3 = S2 - S4/2 and
+// s^4 = 3/8 - C2/2 + C4/8, which differentiate term by term.
+__device__ __forceinline__ void delta_slope(double t, double a, double b, double cc, double beta, double q0,
+                                            double q1, double q2, double q3, double q4, double* g, double* gg) {
+    double S2, C2;
+    sincos(2.0 * t, &S2, &C2);
+    const double C4 = C2 * C2 - S2 * S2, S4 = 2.0 * S2 * C2;
+    const double dq = cc - a;
+    *g = dq * S2 + 2.0 * b * C2 +
+         0.5 * beta * (4.0 * C2 * q0 + 2.0 * S2 * q1 + 2.0 * S4 * q2 + 2.0 * (C2 - C4) * q3 + (S2 - 0.5 * S4) * q4);
+    *gg = 2.0 * dq * C2 - 4.0 * b * S2 +
+          0.5 * beta * (-8.0 * S2 * q0 + 4.0 * C2 * q1 + 8.0 * C4 * q2 + (8.0 * S4 - 4.0 * S2) * q3 +
+                        2.0 * (C2 - C4) * q4);
+}
+
+// Full line search of Section 5.1: the global minimiser of the energy along the great circle.
+// E(t) has period pi (u -> -u keeps E), so [0, pi) is scanned at kFullSamples angles; the slope's
+// zero bracketed between the best angle and the neighbour towards which E falls is then found by
+// Newton steps kept inside the shrinking bracket (bisection when a step leaves it), to the last
+// few ulps.  The result is reduced into [0, pi).
+constexpr int kFullSamples = 64;
+__device__ double theta_full(double a, double b, double cc, double beta, double q0, double q1, double q2, double q3,
+                             double q4) {
+    const double step = 3.141592653589793 / kFullSamples;
+    int kb = 0;
+    double eb = 0.0;  // t = 0 changes nothing
+    for (int k = 1; k < kFullSamples; ++k) {
+        double s, c;
+        sincos(k * step, &s, &c);
+        const double e = delta_energy(c, s, a, b, cc, beta, q0, q1, q2, q3, q4);
+        if (e < eb) {
+            eb = e;
+            kb = k;
+        }
+    }
+    double t = kb * step, g, gg;
+    delta_slope(t, a, b, cc, beta, q0, q1, q2, q3, q4, &g, &gg);
+    double lo = g < 0.0 ? t : t - step, hi = g < 0.0 ? t + step : t;
+    double glo, ghi, unused;
+    delta_slope(lo, a, b, cc, beta, q0, q1, q2, q3, q4, &glo, &unused);
+    delta_slope(hi, a, b, cc, beta, q0, q1, q2, q3, q4, &ghi, &unused);
+    if (g != 0.0 && glo < 0.0 && ghi > 0.0) {
+        for (int it = 0; it < 80; ++it) {
+            if (g == 0.0) break;
+            if (g < 0.0)
+                lo = t;
+            else
+                hi = t;
+            double tn = t - g / gg;
+            if (!(gg > 0.0) || !(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+            if (tn == t || !(hi - lo > 4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)))) break;
+            t = tn;
+            delta_slope(t, a, b, cc, beta, q0, q1, q2, q3, q4, &g, &gg);
+        }
+    }
+    t = fmod(t, 3.141592653589793);
+    return t < 0.0 ? t + 3.141592653589793 : t;
+}
+
+// Sufficient-decrease constant of the Armijo test (the customary value).
+constexpr double kArmijoC1 = 1e-4;
+
 // Step selection (Section 5.1 heuristic; readings: theta_opt = -E'(0)/E''(0) when E''(0) > 0,
 // else theta_default; clamp to (0, pi/2]; halve until E decreases, at most max_halvings times).
+// line_search 1 asks each trial for the Armijo decrease as well; 2 takes the full line search.
 __device__ __forceinline__ void fin_step(Scal& S, const double* t) {
     if (!S.done) {
         const double w = S.cell;
@@ -183,18 +247,31 @@ __device__ __forceinline__ void fin_step(Scal& S, const double* t) {
         th = fmin(fmax(th, 0.0), 1.5707963267948966);
         double acc_t = -1.0, dE = 0.0, c = 1.0, s = 0.0;
         int j = 0;
-        for (; j <= S.max_halvings; ++j) {
-            const double tj = th * ldexp(1.0, -j);
-            if (!(tj > 0.0)) break;
-            double sj, cj;
-            sincos(tj, &sj, &cj);
-            const double e = delta_energy(cj, sj, S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
+        if (S.line_search == 2) {
+            const double tf = theta_full(S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
+            double sf, cf;
+            sincos(tf, &sf, &cf);
+            const double e = delta_energy(cf, sf, S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
             if (e < 0.0) {
-                acc_t = tj;
+                acc_t = tf;
                 dE = e;
-                c = cj;
-                s = sj;
-                break;
+                c = cf;
+                s = sf;
+            }
+        } else {
+            for (; j <= S.max_halvings; ++j) {
+                const double tj = th * ldexp(1.0, -j);
+                if (!(tj > 0.0)) break;
+                double sj, cj;
+                sincos(tj, &sj, &cj);
+                const double e = delta_energy(cj, sj, S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
+                if (e < 0.0 && (S.line_search != 1 || e <= kArmijoC1 * tj * d1)) {
+                    acc_t = tj;
+                    dE = e;
+                    c = cj;
+                    s = sj;
+                    break;
+                }
             }
         }
         S.d2 = d2;

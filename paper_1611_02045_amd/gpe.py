@@ -38,7 +38,8 @@ class PcgOpts(ctypes.Structure):
                 ("tol_energy", ctypes.c_double), ("max_iter", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("beta_rule", ctypes.c_int32), ("switch_res", ctypes.c_double), ("theta_default", ctypes.c_double),
                 ("max_halvings", ctypes.c_int32), ("refresh_every", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("record_history", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("record_history", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("line_search", ctypes.c_int32)]
 
 
 class PcgReport(ctypes.Structure):
@@ -142,6 +143,8 @@ def default_opts(**kw) -> PcgOpts:
             v = {"fp64": 0, "mixed": 1}[v]
         if k == "beta_rule" and isinstance(v, str):
             v = {"pr": 0, "fr": 1}[v]
+        if k == "line_search" and isinstance(v, str):
+            v = {"heuristic": 0, "armijo": 1, "full": 2}[v]
         if not hasattr(o, k):
             raise TypeError(f"unknown solver option {k!r}")
         setattr(o, k, v)

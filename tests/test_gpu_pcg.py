@@ -114,6 +114,47 @@ def test_methods_and_preconditioners(torch_gpu, method, precond):
         assert abs(h["res"] - h_ref["res"]) < 1e-8 * h_ref["res"]
 
 
+@pytest.mark.parametrize("key", ["1d", "2d", "3d"])
+@pytest.mark.parametrize("line_search,beta_rule", [("armijo", "pr"), ("full", "pr"), ("heuristic", "fr"),
+                                                   ("full", "fr")])
+def test_step_rules_trajectory_matches_oracle(torch_gpu, key, line_search, beta_rule):
+    """The Armijo test, the full line search and the Fletcher-Reeves coefficient: the first
+    iterations agree with the oracle's (energy, chemical potential, residual, accepted angle,
+    halvings)."""
+    prob, V, phi0 = _inputs(key)
+    print(f"step rules {key} {line_search} {beta_rule}", flush=True)
+    ref = O.pcg(prob, V, phi0, tol_res=1e-30, max_iter=12, record=True, line_search=line_search,
+                beta_rule=beta_rule)
+    rep, _, hist = _gpu_solve(torch_gpu, prob, V, phi0, tol_res=1e-30, max_iter=12, record_history=1,
+                              check_every=4, line_search=line_search, beta_rule=beta_rule)
+    assert rep["iters"] == 12 and rep["status"] == 1
+    assert len(hist) >= 12
+    for h_ref, h in zip(ref.history, hist):
+        assert abs(h["E"] - h_ref["E"]) < 1e-11 * abs(h_ref["E"])
+        assert abs(h["lam"] - h_ref["lam"]) < 1e-11 * abs(h_ref["lam"])
+        assert abs(h["res"] - h_ref["res"]) < 1e-8 * h_ref["res"] + 1e-13
+        if "theta" in h_ref:
+            assert abs(h["theta"] - h_ref["theta"]) < 1e-7 * h_ref["theta"]
+            assert int(h["halvings"]) == h_ref["halvings"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("line_search", ["armijo", "full"])
+def test_step_rules_converge_to_oracle_state(torch_gpu, precision, line_search):
+    prob, V, phi0 = _inputs("2d")
+    tol = 1e-9
+    print(f"step rules solve {line_search} {precision}", flush=True)
+    ref = O.pcg(prob, V, phi0, tol_res=tol, max_iter=3000, line_search=line_search)
+    rep, phi, _ = _gpu_solve(torch_gpu, prob, V, phi0, tol_res=tol, max_iter=3000, precision=precision,
+                             line_search=line_search)
+    assert ref.status == "converged"
+    assert rep["status"] == 0, rep
+    rel = 1e-10 if precision == "fp64" else 1e-6
+    assert abs(rep["E"] - ref.E) < rel * abs(ref.E)
+    assert abs(O.energy(prob, V, phi) - ref.E) < rel * abs(ref.E)
+    print(f"  iters gpu={rep['iters']} oracle={ref.iters}")
+
+
 def test_beta0_gives_exact_ground_state(torch_gpu):
     """1-D harmonic trap, beta = 0, seeded noisy start: E = 1/2 to 1e-10."""
     prob = Problem(1, (256,), (16.0,), 0.0, 0.0)
