@@ -157,6 +157,8 @@ def main():
     ap.add_argument("--no-nested", action="store_true", help="skip the nested-grid solves")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 64-instance sweep")
     ap.add_argument("--no-configs", action="store_true", help="skip the 1-D, 2-D 256^2 and 3-D single solves")
+    ap.add_argument("--no-step-rules", action="store_true",
+                    help="skip the Armijo / full line search / Fletcher-Reeves solves")
     ap.add_argument("--tol-coarse", type=float, default=1e-5, help="residual tolerance of the coarse nested grids")
     ap.add_argument("--profile-iters", type=int, default=30)
     ap.add_argument("--profile-only", action="store_true",
@@ -226,6 +228,21 @@ def main():
     bad = [r["status"] for r in reps_mixed + reps_fp64 if r["status"] != 0]
     if bad:
         log(f"[bench] WARNING: non-converged statuses {bad}")
+
+    # the step controls and CG coefficient the paper names as alternatives (Sections 5.1-5.2), one
+    # batched mixed step each (outside the timed region): iterations and seconds beside the
+    # heuristic's.  Fletcher-Reeves stalls on most of these starts, so its solves stop at 40 000
+    # iterations (four times the heuristic's longest).
+    step_rules = None
+    if not args.no_step_rules:
+        step_rules = {"heuristic_pr": {"s": mean(t_mixed), "iters": [r["iters"] for r in reps_mixed]}}
+        for tag, extra in (("armijo_pr", {"line_search": "armijo"}), ("full_pr", {"line_search": "full"}),
+                           ("heuristic_fr", {"beta_rule": "fr", "max_iter": 40000})):
+            sec, reps = step({**mixed, **extra})
+            step_rules[tag] = {"s": sec, "iters": [r["iters"] for r in reps],
+                               "converged": sum(r["status"] == 0 for r in reps),
+                               "E_min": min(r["E"] for r in reps)}
+            log(f"[bench] step rule {tag}: {sec:.4f} s, iters {step_rules[tag]['iters']}")
 
     # each start solved alone (one plan, one start at a time)
     single = None
@@ -403,6 +420,7 @@ def main():
         "iters_mixed": {"per_start": it_mixed, "fp32": [r["iters_fp32"] for r in reps_mixed]},
         "iters_fp64": it_fp64,
         "single_start": single,
+        "step_rules": step_rules,
         "nested_grids": nested,
         "sweep_64": sweep,
         "other_configs": configs,

@@ -182,23 +182,28 @@ __device__ __forceinline__ void delta_slope(double t, double a, double b, double
 }
 
 // Full line search of Section 5.1: the global minimiser of the energy along the great circle.
-// E(t) has period pi (u -> -u keeps E), so [0, pi) is scanned at kFullSamples angles; the slope's
-// zero bracketed between the best angle and the neighbour towards which E falls is then found by
-// Newton steps kept inside the shrinking bracket (bisection when a step leaves it), to the last
-// few ulps.  The result is reduced into [0, pi).
+// E(t) has period pi (u -> -u keeps E), so [0, pi) is scanned at kFullSamples angles (the first
+// lowest sample wins); the slope's zero bracketed between the best angle and the neighbour
+// towards which E falls is then found by Newton steps kept inside the shrinking bracket
+// (bisection when a step leaves it), to the last few ulps.  The result is reduced into [0, pi).
+// The scan runs one angle per lane of the first wave when the workgroup has one (full_scan_wave,
+// `kb` >= 0), else serially here.
 constexpr int kFullSamples = 64;
-__device__ double theta_full(double a, double b, double cc, double beta, double q0, double q1, double q2, double q3,
-                             double q4) {
-    const double step = 3.141592653589793 / kFullSamples;
-    int kb = 0;
-    double eb = 0.0;  // t = 0 changes nothing
-    for (int k = 1; k < kFullSamples; ++k) {
-        double s, c;
-        sincos(k * step, &s, &c);
-        const double e = delta_energy(c, s, a, b, cc, beta, q0, q1, q2, q3, q4);
-        if (e < eb) {
-            eb = e;
-            kb = k;
+constexpr double kFullStep = 3.141592653589793 / kFullSamples;
+__device__ double theta_full(int kb, double a, double b, double cc, double beta, double q0, double q1, double q2,
+                             double q3, double q4) {
+    const double step = kFullStep;
+    if (kb < 0) {
+        kb = 0;
+        double eb = 0.0;  // t = 0 changes nothing
+        for (int k = 1; k < kFullSamples; ++k) {
+            double s, c;
+            sincos(k * step, &s, &c);
+            const double e = delta_energy(c, s, a, b, cc, beta, q0, q1, q2, q3, q4);
+            if (e < eb) {
+                eb = e;
+                kb = k;
+            }
         }
     }
     double t = kb * step, g, gg;
@@ -231,7 +236,7 @@ constexpr double kArmijoC1 = 1e-4;
 // Step selection (Section 5.1 heuristic; readings: theta_opt = -E'(0)/E''(0) when E''(0) > 0,
 // else theta_default; clamp to (0, pi/2]; halve until E decreases, at most max_halvings times).
 // line_search 1 asks each trial for the Armijo decrease as well; 2 takes the full line search.
-__device__ __forceinline__ void fin_step(Scal& S, const double* t) {
+__device__ __forceinline__ void fin_step(Scal& S, const double* t, int kb) {
     if (!S.done) {
         const double w = S.cell;
         const double cR = w * t[B_CR], aR = w * t[B_AR], bR = w * t[B_BR];
@@ -248,7 +253,7 @@ __device__ __forceinline__ void fin_step(Scal& S, const double* t) {
         double acc_t = -1.0, dE = 0.0, c = 1.0, s = 0.0;
         int j = 0;
         if (S.line_search == 2) {
-            const double tf = theta_full(S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
+            const double tf = theta_full(kb, S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
             double sf, cf;
             sincos(tf, &sf, &cf);
             const double e = delta_energy(cf, sf, S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
@@ -463,6 +468,32 @@ __device__ __forceinline__ void state_publish(Scal* out, int b, int blk, const S
     for (int c = threadIdx.x; c < kScalChunks; c += blockDim.x) dst[c] = src[c];
 }
 
+// The scan of the full line search on the first wave: lane k evaluates the energy change at
+// k pi / 64 from the same coefficients as fin_step, and an xor butterfly over (change, k) keeps
+// the lowest change, the lowest k among equal ones (what the serial scan keeps).
+__device__ __forceinline__ int full_scan_wave(const Scal& S, const double* t) {
+    static_assert(kFullSamples == 64, "one angle per lane");
+    const int k = threadIdx.x & 63;
+    const double w = S.cell;
+    const double cc = w * t[B_C], b = w * t[B_B];
+    const double SAB = w * t[B_AB], SACA = w * t[B_ACA], SBB = w * t[B_BB], SCAB = w * t[B_CAB],
+                 SCACA = w * t[B_CACA];
+    double s, c;
+    sincos(k * kFullStep, &s, &c);
+    double e = k == 0 ? 0.0 : delta_energy(c, s, S.a, b, cc, S.beta, SAB, SACA, SBB, SCAB, SCACA);
+    int kk = k;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double eo = __shfl_xor(e, off, 64);
+        const int ko = __shfl_xor(kk, off, 64);
+        if (eo < e || (eo == e && ko < kk)) {
+            e = eo;
+            kk = ko;
+        }
+    }
+    return kk;
+}
+
 // The step at the start of phase A, from the direction sums of every pass of phase B (one region,
 // B sums), when they are pending: the line search and the predicted scalars of the new iterate.
 constexpr int kStepRowsPerThread = 16;   // 256 rows with 256-thread blocks
@@ -474,9 +505,14 @@ __device__ __forceinline__ void intake_step(const Scal* in, const Partials& pb, 
 __device__ __forceinline__ void begin_step(const Scal* in, Scal* out, const Partials& pb, int b, int blk, double* red,
                                            Scal* s, const IntakeStep& it) {
     __shared__ double tot[B_K];
-    absorb_finish(in, b, blk, s, it, pb, B_MAXMASK, red, tot, [](Scal& S, const double* t) {
+    it.st.store(in, b, s);
+    it.rows.reduce(pb, b, B_MAXMASK, red, tot);  // ends with a barrier: s and tot are visible
+    int kb = -1;
+    if (s->line_search == 2 && !s->done && s->b_phase && blockDim.x >= 64 && threadIdx.x < 64)
+        kb = full_scan_wave(*s, tot);  // the whole first wave takes this branch (s is uniform)
+    finish<B_K>(s, tot, blk, [kb](Scal& S, const double* t) {
         if (!S.done && S.b_phase) {
-            fin_step(S, t);
+            fin_step(S, t, kb);
             S.b_phase = 0;
         }
     });
