@@ -24,9 +24,12 @@ Geo make_geo(const gpe_problem_t& p) {
     for (int a = 0; a < 3; ++a) {
         if (a < p.dim) {
             g.n[a] = p.n[a];
+            const int f5 = p.n[a] % 5 == 0 ? 1 : 0;
+            const int m = f5 ? p.n[a] / 5 : p.n[a];
             int lg = 0;
-            while ((1 << lg) < p.n[a]) ++lg;
+            while ((1 << lg) < m) ++lg;
             g.lg[a] = lg;
+            g.f5[a] = f5;
             g.L[a] = p.L[a];
             g.h[a] = 2.0 * p.L[a] / p.n[a];
             g.dk[a] = 3.141592653589793238462643383279502884 / p.L[a];
@@ -40,6 +43,7 @@ Geo make_geo(const gpe_problem_t& p) {
             g.dk[a] = 3.141592653589793238462643383279502884;
         }
     }
+    g.pow2 = !(g.f5[0] || g.f5[1] || g.f5[2]);
     return g;
 }
 
@@ -117,8 +121,11 @@ int validate_problem(const gpe_problem_t* p) {
     for (int a = 0; a < p->dim; ++a) {
         const int n = p->n[a];
         if (n < 2 || (n & 1)) { set_error("grid sizes must be even and >= 2"); return GPE_EINVAL; }
-        if ((n & (n - 1)) != 0 || n < 8 || n > 1024) {
-            set_error("grid sizes must be powers of two between 8 and 1024");
+        const bool pow2 = (n & (n - 1)) == 0 && n >= 8 && n <= 1024;
+        const int m = n / 5;
+        const bool five = n % 5 == 0 && (m & (m - 1)) == 0 && n >= 40 && n <= 640;
+        if (!pow2 && !five) {
+            set_error("grid sizes must be 2^k (8 to 1024) or 5 * 2^k (40 to 640)");
             return GPE_EUNSUPPORTED;
         }
         if (!(p->L[a] > 0.0) || !std::isfinite(p->L[a])) { set_error("half-widths L must be positive"); return GPE_EINVAL; }

@@ -38,7 +38,9 @@ template <typename T> __host__ __device__ __forceinline__ C2<T> muli(C2<T> a, T 
 struct Geo {
     int dim;
     int n[3];       // points per axis (1 for unused axes)
-    int lg[3];      // log2 n
+    int lg[3];      // log2 of the power-of-two part of n (n = 2^lg, or 5 * 2^lg when f5)
+    int f5[3];      // 1 when n = 5 * 2^lg (a radix-5 stage ends the line transform)
+    int pow2;       // every axis is a power of two (the line decomposition uses shifts only)
     double L[3];    // half-widths
     double h[3];    // spacings 2L/n
     double dk[3];   // frequency spacings pi/L

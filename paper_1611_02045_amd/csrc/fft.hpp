@@ -1,9 +1,10 @@
 // LDS-staged Stockham FFT of one line held across TPL = M/8 threads (8 points per thread).
 //
-// A line of M = 2^lg complex points (8 <= M <= 1024) is owned by TPL threads; thread t keeps the
-// eight points x[t + s*TPL], s = 0..7, in registers.  The transform is a sequence of Stockham
-// autosort stages: one radix-2 or radix-4 stage when lg is not a multiple of 3, then radix-8
-// stages.  Every stage reads its inputs from the positions t + s*TPL, so the first stage can
+// A line of M = 2^lg complex points (8 <= M <= 1024), or M = 5 * 2^lg (40 <= M <= 640), is owned
+// by TPL threads; thread t keeps the eight points x[t + s*TPL], s = 0..7, in registers.  The
+// transform is a sequence of Stockham autosort stages: one radix-2 or radix-4 stage when lg is
+// not a multiple of 3, then radix-8 stages, and for M = 5 * 2^lg a last radix-5 stage worked in
+// LDS (its 2^lg butterflies are spread over the TPL threads).  Every stage reads its inputs from the positions t + s*TPL, so the first stage can
 // take its operands straight from a coalesced global load, and the last stage leaves
 // X[t + s*TPL] (natural frequency order) in the same registers.  Consequently a spectral
 // multiplier can be applied in registers and an inverse transform can follow with no LDS round
@@ -82,6 +83,27 @@ __host__ __device__ __forceinline__ void dft8(C2<T> (&v)[8]) {
     v[1] = b0; v[3] = b1; v[5] = b2; v[7] = b3;
 }
 
+// In-place 5-point DFT: X_k = sum_r x_r e^{DIR 2 pi i rk/5}.  With c_m = cos(2 pi m/5),
+// s_m = sin(2 pi m/5): X_1,4 = x0 + c1 (x1 + x4) + c2 (x2 + x3) +- DIR i (s1 (x1 - x4) + s2 (x2 - x3))
+// and X_2,3 = x0 + c2 (x1 + x4) + c1 (x2 + x3) +- DIR i (s2 (x1 - x4) - s1 (x2 - x3)).
+template <typename T, int DIR>
+__host__ __device__ __forceinline__ void dft5(C2<T>& x0, C2<T>& x1, C2<T>& x2, C2<T>& x3, C2<T>& x4) {
+    const T c1 = (T)0.309016994374947424102293417182819059;   // cos(2 pi/5)
+    const T c2 = (T)-0.809016994374947424102293417182819059;  // cos(4 pi/5)
+    const T s1 = (T)0.951056516295153572116439333379382143;   // sin(2 pi/5)
+    const T s2 = (T)0.587785252292473129168705954639072769;   // sin(4 pi/5)
+    const C2<T> a1 = add(x1, x4), b1 = sub(x1, x4), a2 = add(x2, x3), b2 = sub(x2, x3);
+    const C2<T> t1 = mk(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+    const C2<T> t2 = mk(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+    const C2<T> u1 = rot90<T, DIR>(mk(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+    const C2<T> u2 = rot90<T, DIR>(mk(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+    x0 = add(x0, add(a1, a2));
+    x1 = add(t1, u1);
+    x4 = sub(t1, u1);
+    x2 = add(t2, u2);
+    x3 = sub(t2, u2);
+}
+
 // Order this wave's LDS accesses (a wave's LDS operations execute in issue order; the fences keep
 // the compiler from moving them across).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -92,11 +114,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Read back v[s] = buf[t + s*TPL] after a stage's scattered write, synchronised on both sides:
 // across the workgroup, or only within the wave when every line lies inside one wave (`wave`).
-// For TPL >= 8, lpad(t + s*TPL) = lpad(t) + s*lpad(TPL): one base and one stride.
+// For TPL a multiple of 8, lpad(t + s*TPL) = lpad(t) + s*lpad(TPL): one base and one stride.
 template <typename T>
 __device__ __forceinline__ void exchange_read(C2<T> (&v)[8], const C2<T>* buf, int t, int TPL, bool wave) {
     if (wave) wave_lds_sync(); else __syncthreads();
-    if (TPL >= 8) {
+    if ((TPL & 7) == 0) {
         const C2<T>* p = buf + lpad(t);
         const int st = lpad(TPL);
 #pragma unroll
@@ -109,13 +131,14 @@ __device__ __forceinline__ void exchange_read(C2<T> (&v)[8], const C2<T>* buf, i
 }
 
 // Full line transform (see file comment).  All threads of the block must call it with the same
-// lg and `wave`; `buf` is this thread's line region in LDS (one padded line) and `tw` the
-// table.  wave: each line is held by threads of a single wave (lines of at most 512 points laid
-// along consecutive lanes), so the exchanges need no workgroup barrier.
+// lg, M (2^lg or 5 * 2^lg) and `wave`; `buf` is this thread's line region in LDS (one padded line)
+// and `tw` the table of M entries.  wave: each line is held by threads of a single wave (lines of
+// at most 512 points laid along consecutive lanes), so the exchanges need no workgroup barrier.
 template <typename T, int DIR>
-__device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, int t, int lg,
+__device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, int t, int lg, int M,
                                          bool wave = false) {
-    const int TPL = 1 << (lg - 3);
+    const bool f5 = M != (1 << lg);
+    const int TPL = M >> 3;
     const int rem = lg % 3;
     const int n8 = lg / 3;
     int lgNs = 0;
@@ -148,7 +171,7 @@ __device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>*
         if (lgNs > 0) {
             // w_r = tw[r * step]: w1, w2, w4 from the table, the other four as products of two
             const int jm = t & ((1 << lgNs) - 1);
-            const int step = jm << (lg - 3 - lgNs);  // jm * M / (8 Ns)
+            const int step = jm * (TPL >> lgNs);  // jm * M / (8 Ns)
             C2<T> w1 = tw[step], w2 = tw[2 * step], w4 = tw[4 * step];
             if (DIR > 0) {
                 w1.y = -w1.y;
@@ -165,7 +188,7 @@ __device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>*
             v[7] = mul(v[7], mul(w3, w4));
         }
         dft8<T, DIR>(v);
-        if (k + 1 < n8) {
+        if (k + 1 < n8 || f5) {
             const int Ns = 1 << lgNs;
             const int base = ((t >> lgNs) << (lgNs + 3)) + (t & (Ns - 1));
             if (Ns == 1 || Ns >= 8) {
@@ -179,9 +202,30 @@ __device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>*
 #pragma unroll
                 for (int r = 0; r < 8; ++r) buf[lpad(base + r * Ns)] = v[r];
             }
-            exchange_read(v, buf, t, TPL, wave);
+            if (k + 1 < n8) exchange_read(v, buf, t, TPL, wave);
         }
         lgNs += 3;
+    }
+    if (f5) {
+        // radix-5 stage at Ns = P = 2^lg = M/5: butterfly j < P takes the points j + r P, twiddles
+        // them by e^{-+2 pi i jr/M} and writes its outputs back to the same places (natural order)
+        const int P = 1 << lg;
+        if (wave) wave_lds_sync(); else __syncthreads();
+        for (int j = t; j < P; j += TPL) {
+            C2<T> x[5];
+#pragma unroll
+            for (int r = 0; r < 5; ++r) x[r] = buf[lpad(j + r * P)];
+#pragma unroll
+            for (int r = 1; r < 5; ++r) {
+                C2<T> w = tw[j * r];
+                if (DIR > 0) w.y = -w.y;
+                x[r] = mul(x[r], w);
+            }
+            dft5<T, DIR>(x[0], x[1], x[2], x[3], x[4]);
+#pragma unroll
+            for (int r = 0; r < 5; ++r) buf[lpad(j + r * P)] = x[r];
+        }
+        exchange_read(v, buf, t, TPL, wave);
     }
 }
 

@@ -72,23 +72,30 @@ inline bool valid_lines(const Geo& g, int AX, int complex_bytes, int C) {
     return pass_lds_bytes_cb(complex_bytes, g.n[AX], C, C * TPL, 32, AX) <= kPassLdsBudget;
 }
 
+// Largest power of two <= x (x >= 1).
+inline int floor_pow2(int x) {
+    int p = 1;
+    while (2 * p <= x) p *= 2;
+    return p;
+}
+
 inline int pass_lines_rule(const Geo& g, int AX, int complex_bytes, int B) {
     const int TPL = g.n[AX] / 8;
     const int64_t lpf = lines_per_field(g, AX);
     const int64_t lines = lpf * (int64_t)B;
     int C;
     if (AX == 0) {
-        C = std::max(1, 256 / TPL);
+        C = floor_pow2(std::max(1, 256 / TPL));
     } else {
         C = std::max(1, 128 / complex_bytes);
-        C = std::min(C, std::max(1, 256 / TPL));
-        C = std::min(C, g.n[0]);
+        C = std::min(C, floor_pow2(std::max(1, 256 / TPL)));
+        C = std::min(C, floor_pow2(g.n[0]));
     }
     // keep at least 64 workgroups so that small grids still spread over the chip, but never less
     // than one full wave per workgroup: a partial wave leaves lanes idle and takes the slow
     // partial-row reduction; larger groups keep the per-instance partial rows (which every
-    // consumer workgroup reduces) few
-    const int Cmin = std::max(1, 64 / TPL);
+    // consumer workgroup reduces) few.  (Lines of 5 * 2^k points give partial waves regardless.)
+    const int Cmin = floor_pow2(std::max(1, 64 / TPL));
     while (C > Cmin && lines / C < 64) C >>= 1;
     while (C > 1 && (lpf % C) != 0) C >>= 1;
     // keep the LDS footprint (twiddles + lines + reduction scratch) within budget
@@ -129,7 +136,7 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
     const bool early = blocks <= device_cus();
     // lines of 512 points (the common size) take the compile-time transform
     constexpr int kLG = 9;
-    const bool ct = g.lg[AX] == kLG;
+    const bool ct = g.lg[AX] == kLG && !g.f5[AX];
     using K = decltype(&pass_kernel<T, AX, Op, kMaxPassThreads, true, 0>);
     const K variants[4] = {pass_kernel<T, AX, Op, kMaxPassThreads, false, 0>,
                            pass_kernel<T, AX, Op, kMaxPassThreads, true, 0>,

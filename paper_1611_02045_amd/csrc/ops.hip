@@ -45,7 +45,7 @@ struct OpApply {
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
                              const C2<T>*) const {
         const double rot = rot_coef<AX>(g, lc, omega);
-        const double inv = ldexp(1.0, -lc.lg);  // 1/M, exact
+        const double inv = 1.0 / lc.M;  // 1/M (exact for M = 2^k)
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const double xi = freq_of(lc.k(s), lc.M, g.dk[AX]);
@@ -143,7 +143,7 @@ struct OpProlong {
     template <int LG>
     __device__ void spectral(const Geo&, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
                              const C2<T>* tw) const {
-        const T inv = (T)ldexp(1.0, -lc.lg);  // 1/M, exact
+        const T inv = (T)(1.0 / lc.M);  // 1/M (exact for M = 2^k)
         const C2<T> half{(T)hr, (T)hi};
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -300,7 +300,7 @@ struct OpEnergy {
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&acc)[4], C2<T>*,
                              const C2<T>*) const {
         const double rot = rot_coef<AX>(g, lc, omega);
-        const double inv = ldexp(1.0, -lc.lg);  // 1/M, exact
+        const double inv = 1.0 / lc.M;  // 1/M (exact for M = 2^k)
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const double xi = freq_of(lc.k(s), lc.M, g.dk[AX]);
@@ -433,7 +433,7 @@ struct OpPre {
             const double mu = freq_of(lc.i2, g.n[1], g.dk[1]);
             ko = xi * xi + mu * mu;
         }
-        const double invN = ldexp(1.0, -(g.lg[0] + g.lg[1] + g.lg[2]));  // 1/N, exact
+        const double invN = 1.0 / (double)g.N;  // 1/N (exact for powers of two)
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const double k = freq_of(lc.k(s), lc.M, g.dk[AX]);

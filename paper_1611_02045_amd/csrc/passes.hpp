@@ -40,19 +40,26 @@ __host__ __device__ inline int64_t lines_per_field(const Geo& g, int AX) {
     return g.N / g.n[AX];
 }
 
-// Every extent is a power of two, so the decomposition of the launch into lines uses shifts and
-// masks only (64-bit integer division is a long software sequence on the GPU).  blk receives the
-// workgroup's index within its instance.
+// When every extent is a power of two the decomposition of the launch into lines uses shifts and
+// masks only (64-bit integer division is a long software sequence on the GPU); grids with an axis
+// of 5 * 2^k points take 32-bit divisions (line counts stay far below 2^32).  blk receives the
+// workgroup's index within its instance.  C (lines per workgroup) is always a power of two.
 template <int AX, int LG = 0>
 __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
     LineCtx lc;
     lc.lg = LG > 0 ? LG : g.lg[AX];  // a compile-time size folds every index below
-    lc.M = 1 << lc.lg;
+    const bool f5 = LG == 0 && g.f5[AX];
+    lc.M = f5 ? 5 << lc.lg : 1 << lc.lg;
     lc.TPL = lc.M >> 3;
-    lc.wave = AX == 0 && lc.TPL <= 64;  // x lines take consecutive lanes, TPL of them per line
+    // x lines take consecutive lanes, TPL of them per line; lines of 5 * 2^k points can straddle
+    // waves
+    lc.wave = AX == 0 && !f5 && lc.TPL <= 64;
     const int lgC = __ffs(C) - 1;
     const int tid = threadIdx.x;
-    if (AX == 0) {
+    if (AX == 0 && f5) {
+        lc.c = tid / lc.TPL;
+        lc.t = tid - lc.c * lc.TPL;
+    } else if (AX == 0) {
         lc.c = tid >> (lc.lg - 3);
         lc.t = tid & (lc.TPL - 1);
     } else {
@@ -66,12 +73,35 @@ __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
     // x * G/8 + j runs as workgroup 8 j + x, and the XCD's L2 serves each line to all of them.
     unsigned grp = blockIdx.x;
     if (AX != 0 && (gridDim.x & 7u) == 0) grp = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const int nx = g.n[0], ny = g.n[1];
+    if (!g.pow2) {
+        const unsigned lpf = (unsigned)(g.N / lc.M);
+        const unsigned line = (grp << lgC) + (unsigned)lc.c;
+        lc.b = (int)(line / lpf);
+        const unsigned lf = line - (unsigned)lc.b * lpf;
+        blk = (int)(lf >> lgC);
+        lc.off_b = (int64_t)lc.b * g.N;
+        const unsigned q = lf / (unsigned)(AX == 0 ? ny : nx);
+        const int r = (int)(lf - q * (unsigned)(AX == 0 ? ny : nx));
+        lc.i1 = r;
+        lc.i2 = (int)q;
+        if (AX == 0) {
+            lc.base = lc.off_b + (int64_t)lf * nx;
+            lc.stride = 1;
+        } else if (AX == 1) {
+            lc.base = lc.off_b + (int64_t)q * nx * ny + r;
+            lc.stride = nx;
+        } else {
+            lc.base = lc.off_b + (int64_t)q * nx + r;
+            lc.stride = (int64_t)nx * ny;
+        }
+        return lc;
+    }
     const int64_t line = ((int64_t)grp << lgC) + lc.c;
     lc.b = (int)(line >> lg_lpf);
     const int64_t lf = line & (((int64_t)1 << lg_lpf) - 1);
     blk = (int)(lf >> lgC);
     lc.off_b = (int64_t)lc.b * g.N;
-    const int nx = g.n[0], ny = g.n[1];
     if (AX == 0) {
         lc.i1 = (int)(lf & (ny - 1));
         lc.i2 = (int)(lf >> g.lg[1]);
@@ -97,7 +127,7 @@ __device__ __forceinline__ void line_fft(C2<T> (&v)[8], C2<T>* buf, const C2<T>*
     if constexpr (LG > 0)
         fft_line_ct<T, DIR, LG, AX == 0 && LG <= 9>(v, buf, tw, lc.t);
     else
-        fft_line<T, DIR>(v, buf, tw, lc.t, lc.lg, lc.wave);
+        fft_line<T, DIR>(v, buf, tw, lc.t, lc.lg, lc.M, lc.wave);
 }
 
 // Dynamic LDS layout of a pass: [twiddles M][lines C * line_stride(M)][reduction scratch].

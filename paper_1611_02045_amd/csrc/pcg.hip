@@ -593,7 +593,7 @@ struct OpResid {
                              const C2<T>*) const {
         if constexpr (ONE) {
             const Scal& s = *lc.sc;
-            const double invN = ldexp(1.0, -lc.lg);  // 1/M, exact
+            const double invN = 1.0 / lc.M;  // 1/M (exact for M = 2^k)
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const double k = freq_of(lc.k(q), lc.M, s.dk[0]);
@@ -673,7 +673,7 @@ struct OpPMid {
                 const double mu = freq_of(lc.i2, g.n[1], s.dk[1]);
                 ko = xi * xi + mu * mu;
             }
-            const double invN = ldexp(1.0, -(g.lg[0] + g.lg[1] + g.lg[2]));  // 1/N, exact
+            const double invN = 1.0 / (double)g.N;  // 1/N (exact for powers of two)
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const double k = freq_of(lc.k(q), lc.M, s.dk[AX]);
@@ -836,7 +836,7 @@ struct OpLp {
                              C2<T>* buf, const C2<T>* tw) const {
         const Scal& s = *lc.sc;
         const double rot = rot_coef_s<AX>(s, lc);
-        const double invM = ldexp(1.0, -lc.lg);  // 1/M, exact
+        const double invM = 1.0 / lc.M;  // 1/M (exact for M = 2^k)
         if (AX < 2 && s.omega != 0.0 && s.dim >= 2) {
             C2<T> u[8];
 #pragma unroll

@@ -77,6 +77,9 @@ def test_struct_layouts_match_header(gpe, tmp_path):
     (1, (16,), (1,), 0.5, -1),                 # rotation in 1-D
     (2, (16, 16), (1.0, -1.0), 0.0, -1),       # negative half-width
     (2, (2048, 8), (1.0, 1.0), 0.0, -2),       # too large
+    (2, (20, 8), (1.0, 1.0), 0.0, -2),         # 5 * 4: below the smallest radix-5 line (40)
+    (1, (1280,), (1.0,), 0.0, -2),             # 5 * 256: above the largest radix-5 line (640)
+    (1, (48,), (1.0,), 0.0, -2),               # 3 * 16
 ])
 def test_invalid_problems_are_rejected_on_the_host(gpe, dim, n, L, omega, status):
     prob = gpe.make_problem(dim, n, L, 1.0, omega)

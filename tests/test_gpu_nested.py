@@ -24,6 +24,12 @@ SHAPES = [
     (3, (8, 8, 8), (3.0, 3.0, 3.0)),
     (3, (16, 32, 8), (4.0, 5.0, 3.0)),
     (3, (64, 64, 64), (8.0, 8.0, 8.0)),
+    # 5 * 2^k points: 40 -> 80, 320 -> 640 (the paper's finest grid), mixed with powers of two
+    (1, (40,), (4.0,)),
+    (1, (320,), (16.0,)),
+    (2, (320, 320), (20.0, 20.0)),
+    (2, (40, 64), (4.0, 6.0)),
+    (3, (40, 16, 80), (4.0, 3.0, 5.0)),
 ]
 IDS = ["x".join(map(str, s[1])) for s in SHAPES]
 TOL = {"f64": 1e-12, "f32": 1e-5}

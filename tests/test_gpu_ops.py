@@ -28,6 +28,16 @@ SHAPES = [
     (3, (8, 8, 8), (3.0, 3.0, 3.0)),
     (3, (16, 32, 8), (4.0, 5.0, 3.0)),
     (3, (64, 64, 64), (8.0, 8.0, 8.0)),
+    # lines of 5 * 2^k points (radix-5 stage): smallest, largest, mixed with powers of two
+    (1, (40,), (4.0,)),
+    (1, (640,), (20.0,)),
+    (2, (640, 640), (20.0, 20.0)),
+    (2, (80, 40), (5.0, 4.0)),
+    (2, (640, 32), (16.0, 6.0)),
+    (2, (32, 640), (6.0, 16.0)),
+    (2, (512, 160), (16.0, 8.0)),
+    (3, (40, 80, 40), (4.0, 5.0, 4.0)),
+    (3, (160, 16, 320), (8.0, 3.0, 10.0)),
 ]
 IDS = ["x".join(map(str, s[1])) for s in SHAPES]
 TOL = {"f64": 2e-12, "f32": 2e-5}
@@ -93,7 +103,8 @@ def test_energy_matches_oracle(torch_gpu, dim, n, L, dtype):
 
 PRECOND_SHAPES = {"1d": (1, (256,), (16.0,)), "2d-aniso": (2, (16, 64), (4.0, 6.0)), "2d": (2, (256, 256), (16.0, 16.0)),
                   "2d-512x": (2, (512, 32), (16.0, 6.0)), "2d-512y": (2, (32, 512), (6.0, 16.0)),
-                  "3d": (3, (16, 32, 8), (4.0, 5.0, 3.0))}
+                  "3d": (3, (16, 32, 8), (4.0, 5.0, 3.0)), "2d-640": (2, (640, 640), (20.0, 20.0)),
+                  "2d-5x": (2, (80, 40), (5.0, 4.0)), "3d-5": (3, (40, 80, 40), (4.0, 5.0, 4.0))}
 
 
 @pytest.mark.parametrize("kind", ["none", "kinetic", "potential", "combined", "c1", "c2"])

@@ -74,6 +74,25 @@ def test_thomas_fermi_start_solves_to_tolerance(torch_gpu, trap):
     assert abs(O.energy(prob, V, out) - rep["E"]) < 1e-12 * abs(rep["E"])
 
 
+def test_fast_rotation_in_quartic_trap_640(torch_gpu):
+    """The same example on the paper's own grid, 640^2 points of [-20, 20]^2 (every transform ends
+    in a radix-5 stage): FP64 PCG reaches ||r||_inf <= 1e-8 and the oracle confirms the state."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, start = workload_quartic_2d(640, 2.0, 1000.0)
+    plan = gpe.Plan.from_problem(prob, "f64")
+    phi = _to(torch, start)
+    print("quartic 640^2 Omega=2", flush=True)
+    rep = plan.pcg_solve(_to(torch, V), phi, tol=1e-8, max_iter=50000)
+    assert rep["status_name"] == "ok"
+    out = phi.cpu().numpy()
+    r, _ = O.residual(prob, V, out)
+    assert np.max(np.abs(r)) < 1.5e-8
+    parts = O.energy_parts(prob, V, out)
+    assert abs(parts.total - rep["E"]) < 1e-12 * abs(rep["E"])
+    assert parts.rotation < -1.0
+
+
 def test_fast_rotation_in_quartic_trap_512(torch_gpu):
     """The paper's fast-rotation example (alpha = 1.2, kappa = 0.3, eta = 1000) at Omega = 2 on
     512^2 points of [-20, 20]^2 from Thomas-Fermi data: FP64 PCG reaches ||r||_inf <= 1e-8, the oracle

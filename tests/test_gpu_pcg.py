@@ -47,6 +47,10 @@ CASES = {
     "2d": (Problem(2, (64, 64), (8.0, 8.0), 100.0, 0.5), "2d"),
     "2d-aniso": (Problem(2, (64, 32), (8.0, 6.0), 60.0, 0.3), "2d"),
     "3d": (Problem(3, (16, 16, 16), (5.0, 5.0, 5.0), 40.0, 0.4), "3d"),
+    # lines of 5 * 2^k points (radix-5 stage in every transform)
+    "1d-640": (Problem(1, (640,), (16.0,), 250.0, 0.0), "1d"),
+    "2d-80x40": (Problem(2, (80, 40), (8.0, 6.0), 100.0, 0.5), "2d"),
+    "3d-40": (Problem(3, (40, 16, 40), (5.0, 5.0, 5.0), 40.0, 0.4), "3d"),
 }
 
 
