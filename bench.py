@@ -345,6 +345,14 @@ def main():
         configs["2d_256_mixed"] = timed_solve(p2, V2, f2, "f64", tol=1e-8, max_iter=200000, precision="mixed")
         p3, V3, f3 = workload_3d(128)
         configs["3d_128_mixed"] = timed_solve(p3, V3, f3, "f64", tol=1e-8, max_iter=200000, precision="mixed")
+        # the paper's fast-rotation example (harmonic + quartic trap, eta = 1000, Omega = 2, Thomas-Fermi
+        # start) on its own grid, 640^2 points of [-20, 20]^2 (radix-5 transforms), and on 512^2
+        from gpe_inputs import workload_quartic_2d
+        for m in (640, 512):
+            pq, Vq, fq = workload_quartic_2d(m, 2.0, 1000.0)
+            for prec in ("fp64", "mixed"):
+                configs[f"2d_{m}_quartic_omega2_{prec}"] = timed_solve(pq, Vq, fq, "f64", tol=1e-8, max_iter=200000,
+                                                                      precision=prec)
         for k, v in configs.items():
             log(f"[bench] config {k}: {v['s']:.4f} s, {v['iters']} iterations, E = {v['E']:.10f}, {v['status']}")
 
@@ -361,6 +369,17 @@ def main():
     bphi32 = phi32.unsqueeze(0).repeat(batch, 1, 1).contiguous()
     apb64, tb64 = applies_per_s(torch, plan64, bphi64, V, 20, batched=True)
     apb32, tb32 = applies_per_s(torch, plan32, bphi32, V32, 20, batched=True)
+    # the same on the paper's 640^2 grid (every line transform ends in a radix-5 stage)
+    ap640 = None
+    if not args.no_configs:
+        from gpe_inputs import workload_quartic_2d
+        pq, Vq, fq = workload_quartic_2d(640, 2.0, 1000.0)
+        ap640 = {}
+        for dt, cd, rd in (("f64", torch.complex128, torch.float64), ("f32", torch.complex64, torch.float32)):
+            pl = gpe.Plan.from_problem(pq, dt)
+            ap640[dt], _ = applies_per_s(torch, pl, torch.from_numpy(fq).to("cuda", cd),
+                                         torch.from_numpy(Vq).to("cuda", rd), 400)
+        log(f"[bench] H applies at 640^2: {ap640}")
     apg64 = apg32 = None
     try:
         apg64 = applies_per_s_graph(torch, plan64, phi0, V)
@@ -426,7 +445,7 @@ def main():
         "other_configs": configs,
         "pcg_iters_per_s_step": {"mixed": max(it_mixed) / mean(t_mixed), "fp64": max(it_fp64) / mean(t_fp64)},
         "h_applies_per_s": {"fp64": ap64, "fp32": ap32, "fp64_batch32": apb64, "fp32_batch32": apb32,
-                            "fp64_graph1000": apg64, "fp32_graph1000": apg32},
+                            "fp64_graph1000": apg64, "fp32_graph1000": apg32, "at_640x640": ap640},
         "h_apply_batch32_hbm_gbs": {
             "fp64": 11 * 8 * 512 * 512 * batch / tb64 / 1e9, "fp32": 11 * 4 * 512 * 512 * batch / tb32 / 1e9},
         "final": {"E_mixed": [r["E"] for r in reps_mixed], "res_mixed": max(r["res_inf"] for r in reps_mixed),

@@ -242,7 +242,7 @@ def thomas_fermi(prob: Problem, V: np.ndarray, gammas=(1.0, 1.0, 1.0)) -> np.nda
 def workload_quartic_2d(M: int = 512, omega: float = 2.0, beta: float = 1000.0, L: float = 20.0):
     """The paper's fast-rotation example in 2-D: harmonic plus quartic trap (alpha = 1.2,
     kappa = 0.3), Thomas-Fermi start, on [-L, L]^2 with M^2 points (the paper: L = 20, h = 1/16,
-    i.e. M = 640; power-of-two grids here)."""
+    i.e. M = 640)."""
     prob = Problem(2, (M, M), (L, L), beta, omega)
     V = quartic_potential(prob)
     return prob, V, thomas_fermi(prob, V)
