@@ -25,7 +25,8 @@
  * gpe_last_error() returns a thread-local message describing the last error.  No C++ exception
  * crosses this boundary.
  *
- * Supported grids: dim in {1, 2, 3}; every n_a a power of two with 8 <= n_a <= 1024.
+ * Supported grids: dim in {1, 2, 3}; every n_a either a power of two with 8 <= n_a <= 1024 or
+ * 5 * 2^k with 40 <= n_a <= 640 (the paper's M = 640 grids); other sizes give GPE_EUNSUPPORTED.
  */
 #ifndef GPE_H
 #define GPE_H
