@@ -307,6 +307,9 @@ FULL_SEARCH_SAMPLES = 64
 # Sufficient-decrease constant of the Armijo test (the paper names the test, not the constant;
 # reading: the customary 1e-4).
 ARMIJO_C1 = 1e-4
+# Curvature constant of the strong Wolfe conditions (reading: 0.1, the usual choice for nonlinear
+# conjugate gradients, below the 1/2 that keeps their directions descent directions).
+WOLFE_C2 = 0.1
 
 
 def theta_full(prob, V, phi, phat, Lphi, Lphat, samples: int = FULL_SEARCH_SAMPLES) -> float:
@@ -349,6 +352,56 @@ def trial_ladder(prob, phi, phat, Lphi, Lphat, theta: float, d1: float, max_halv
     return None, max_halvings
 
 
+def wolfe_search(prob, V, phi, phat, Lphi, Lphat, theta: float, d1: float, max_steps: int):
+    """A step satisfying the strong Wolfe conditions (named in Section 5.1 as an acceptance rule):
+        f(t) <= ARMIJO_C1 t f'(0)  and  |f'(t)| <= -WOLFE_C2 f'(0),   f(t) = E(t) - E(0),
+    by the textbook bracketing search (readings: start at the heuristic's trial theta, double the
+    step while it is too short, at most up to pi/2, where a step that still descends is taken) and
+    a zoom by bisection of the bracket (the midpoint of the two ends each time), at most max_steps
+    evaluations in each phase.  f is energy_change, f' is energy_slope.  Returns (t, evaluations)
+    or (None, evaluations)."""
+    half_pi = 0.5 * math.pi
+    f = lambda t: energy_change(prob, phi, phat, Lphi, Lphat, t)
+    g = lambda t: energy_slope(prob, V, phi, phat, t)
+    armijo = lambda t, ft: ft <= ARMIJO_C1 * t * d1
+    curv = lambda gt: abs(gt) <= -WOLFE_C2 * d1
+
+    def zoom(lo, f_lo, hi, n):
+        for _ in range(max_steps):
+            t = 0.5 * (lo + hi)
+            n += 1
+            ft = f(t)
+            if not armijo(t, ft) or ft >= f_lo:
+                hi = t
+            else:
+                gt = g(t)
+                if curv(gt):
+                    return t, n
+                if gt * (hi - lo) >= 0.0:
+                    hi = lo
+                lo, f_lo = t, ft
+        return None, n
+
+    t_prev, f_prev = 0.0, 0.0
+    t = min(theta, half_pi)
+    n = 0
+    for i in range(max_steps):
+        n += 1
+        ft = f(t)
+        if not armijo(t, ft) or (i > 0 and ft >= f_prev):
+            return zoom(t_prev, f_prev, t, n)
+        gt = g(t)
+        if curv(gt):
+            return t, n
+        if gt >= 0.0:
+            return zoom(t, ft, t_prev, n)
+        if t >= half_pi:
+            return t, n
+        t_prev, f_prev = t, ft
+        t = min(2.0 * t, half_pi)
+    return None, n
+
+
 # ----------------------------------------------------------------------------------------------
 # PG / PCG on the sphere (Algorithms 1 and 2, Sections 5.1-5.3)
 # ----------------------------------------------------------------------------------------------
@@ -387,14 +440,16 @@ def pcg(prob, V, phi0, *, method: str = "pcg", precond: str = "combined", tol_re
         (the Armijo test the section names as an alternative), halving as above;
         line_search="full" takes theta_full (the full line search of the section), accepted
         when it decreases the energy, else the run stops with status "linesearch";
+        line_search="wolfe" takes wolfe_search from the same trial (max_halvings bounds each of
+        its phases; halvings records its evaluations);
       * phi is renormalised after every step;
       * stop when ||r_n||_inf <= tol_res at the top of iteration n (or, when tol_energy > 0,
         when |E_{n+1} - E_n| <= tol_energy).
     """
     if method not in ("pg", "pcg"):
         raise ValueError("method must be 'pg' or 'pcg'")
-    if line_search not in ("heuristic", "armijo", "full"):
-        raise ValueError("line_search must be 'heuristic', 'armijo' or 'full'")
+    if line_search not in ("heuristic", "armijo", "full", "wolfe"):
+        raise ValueError("line_search must be 'heuristic', 'armijo', 'full' or 'wolfe'")
     phi = np.array(phi0, dtype=np.complex128, copy=True)
     phi /= norm(prob, phi)
     r_prev = p_prev = None
@@ -451,6 +506,10 @@ def pcg(prob, V, phi0, *, method: str = "pcg", precond: str = "combined", tol_re
         if line_search == "full":
             t = theta_full(prob, V, phi, phat, Lphi, Lphat)
             accepted = t if energy_change(prob, phi, phat, Lphi, Lphat, t) < 0.0 else None
+        elif line_search == "wolfe":
+            accepted, j = wolfe_search(prob, V, phi, phat, Lphi, Lphat, theta, d1, max_halvings)
+            if accepted is not None:
+                halvings += j
         else:
             accepted, j = trial_ladder(prob, phi, phat, Lphi, Lphat, theta, d1, max_halvings,
                                        armijo=line_search == "armijo")

@@ -263,7 +263,32 @@ def test_armijo_rejects_a_trial_the_decrease_test_accepts():
     assert O.energy_along(prob, V, phi, phat, prev) - E0 > O.ARMIJO_C1 * prev * d1
 
 
-@pytest.mark.parametrize("line_search", ["heuristic", "armijo", "full"])
+@pytest.mark.parametrize("start", ["short", "long"])
+@pytest.mark.parametrize("seed,beta,omega", [(60, 300.0, 0.5), (64, 1200.0, 0.9)])
+def test_wolfe_step_satisfies_the_strong_wolfe_conditions(start, seed, beta, omega):
+    """Checked with plain energies and central-difference slopes only: from a trial far too short
+    (the bracketing must expand it) and from pi/2 (the zoom must shrink it), the accepted step
+    satisfies E(t) - E(0) <= c1 t E'(0) and |E'(t)| <= -c2 E'(0)."""
+    prob, V, phi, phat, Lphi, Lphat = _circle_case(seed, beta, omega)
+    if O.energy_slope(prob, V, phi, phat, 0.0) > 0.0:
+        phat, Lphat = -phat, -Lphat
+    h = 1e-5
+    E0 = O.energy(prob, V, phi)
+    slope = lambda t: (O.energy_along(prob, V, phi, phat, t + h) - O.energy_along(prob, V, phi, phat, t - h)) / (2 * h)
+    d1 = slope(0.0)
+    tmin = O.theta_full(prob, V, phi, phat, Lphi, Lphat)
+    theta = 1e-3 * tmin if start == "short" else 0.5 * math.pi
+    t, n = O.wolfe_search(prob, V, phi, phat, Lphi, Lphat, theta, d1, 30)
+    assert t is not None and n >= 2
+    assert (t > theta) if start == "short" else (t < theta)
+    assert O.energy_along(prob, V, phi, phat, t) - E0 <= O.ARMIJO_C1 * t * d1
+    assert abs(slope(t)) <= -O.WOLFE_C2 * d1 * (1 + 1e-6)
+    # the trial itself violates them (so the search did work)
+    ft = O.energy_along(prob, V, phi, phat, theta) - E0
+    assert ft > O.ARMIJO_C1 * theta * d1 or abs(slope(theta)) > -O.WOLFE_C2 * d1
+
+
+@pytest.mark.parametrize("line_search", ["heuristic", "armijo", "full", "wolfe"])
 @pytest.mark.parametrize("beta_rule", ["pr", "fr"])
 def test_step_rules_reach_the_same_ground_state(line_search, beta_rule):
     """Every step control and CG coefficient ends at the non-rotating ground state: lambda is the
