@@ -142,8 +142,11 @@ typedef struct gpe_pcg_opts {
                             * 1 = the same trials under the Armijo test
                             * E(t) - E(0) <= 1e-4 t E'(0); 2 = full line search: the global
                             * minimiser over [0, pi) of E(cos t phi + sin t phat), accepted when it
-                            * lowers E (one evaluation of the exact energy polynomial per angle,
-                            * no extra pass over the fields) */
+                            * lowers E; 3 = a step satisfying the strong Wolfe conditions
+                            * (c1 = 1e-4, c2 = 0.1) found by bracketing from theta_opt (up to pi/2)
+                            * and bisection, at most max_halvings evaluations per phase, counted
+                            * as halvings.  All evaluate the exact energy polynomial of the
+                            * direction pass: no extra pass over the fields */
 } gpe_pcg_opts_t;
 
 typedef struct gpe_pcg_report {

@@ -232,10 +232,89 @@ __device__ double theta_full(int kb, double a, double b, double cc, double beta,
 
 // Sufficient-decrease constant of the Armijo test (the customary value).
 constexpr double kArmijoC1 = 1e-4;
+// Curvature constant of the strong Wolfe conditions (the usual nonlinear-CG value, below 1/2).
+constexpr double kWolfeC2 = 0.1;
+
+// A step satisfying the strong Wolfe conditions f(t) <= c1 t f'(0), |f'(t)| <= -c2 f'(0) for the
+// energy change f along the great circle: bracketing from the heuristic's trial (doubled while it
+// is too short, up to pi/2, where a step that still descends is taken), then a zoom that bisects
+// the bracket; at most max_steps evaluations in each phase.  Returns the step, or -1 when none was
+// found; *nev receives the number of evaluations.
+__device__ double theta_wolfe(double th, double d1, int max_steps, int* nev, double a, double b, double cc,
+                              double beta, double q0, double q1, double q2, double q3, double q4) {
+    const double half_pi = 1.5707963267948966;
+    auto f = [&](double t) {
+        double s, c;
+        sincos(t, &s, &c);
+        return delta_energy(c, s, a, b, cc, beta, q0, q1, q2, q3, q4);
+    };
+    auto g = [&](double t) {
+        double gv, unused;
+        delta_slope(t, a, b, cc, beta, q0, q1, q2, q3, q4, &gv, &unused);
+        return gv;
+    };
+    const double curv = -kWolfeC2 * d1;
+    int n = 0;
+    double result = -1.0, lo = 0.0, f_lo = 0.0, hi = 0.0;
+    bool zoom = false;
+    double t_prev = 0.0, f_prev = 0.0, t = fmin(th, half_pi);
+    for (int i = 0; i < max_steps; ++i) {
+        ++n;
+        const double ft = f(t);
+        if (!(ft <= kArmijoC1 * t * d1) || (i > 0 && ft >= f_prev)) {
+            lo = t_prev;
+            f_lo = f_prev;
+            hi = t;
+            zoom = true;
+            break;
+        }
+        const double gt = g(t);
+        if (fabs(gt) <= curv) {
+            result = t;
+            break;
+        }
+        if (gt >= 0.0) {
+            lo = t;
+            f_lo = ft;
+            hi = t_prev;
+            zoom = true;
+            break;
+        }
+        if (t >= half_pi) {
+            result = t;
+            break;
+        }
+        t_prev = t;
+        f_prev = ft;
+        t = fmin(2.0 * t, half_pi);
+    }
+    if (zoom) {
+        for (int k = 0; k < max_steps; ++k) {
+            const double tm = 0.5 * (lo + hi);
+            ++n;
+            const double fm = f(tm);
+            if (!(fm <= kArmijoC1 * tm * d1) || fm >= f_lo) {
+                hi = tm;
+            } else {
+                const double gm = g(tm);
+                if (fabs(gm) <= curv) {
+                    result = tm;
+                    break;
+                }
+                if (gm * (hi - lo) >= 0.0) hi = lo;
+                lo = tm;
+                f_lo = fm;
+            }
+        }
+    }
+    *nev = n;
+    return result;
+}
 
 // Step selection (Section 5.1 heuristic; readings: theta_opt = -E'(0)/E''(0) when E''(0) > 0,
 // else theta_default; clamp to (0, pi/2]; halve until E decreases, at most max_halvings times).
-// line_search 1 asks each trial for the Armijo decrease as well; 2 takes the full line search.
+// line_search 1 asks each trial for the Armijo decrease as well; 2 takes the full line search; 3
+// the strong Wolfe search (its evaluations are counted as halvings).
 __device__ __forceinline__ void fin_step(Scal& S, const double* t, int kb) {
     if (!S.done) {
         const double w = S.cell;
@@ -252,12 +331,15 @@ __device__ __forceinline__ void fin_step(Scal& S, const double* t, int kb) {
         th = fmin(fmax(th, 0.0), 1.5707963267948966);
         double acc_t = -1.0, dE = 0.0, c = 1.0, s = 0.0;
         int j = 0;
-        if (S.line_search == 2) {
-            const double tf = theta_full(kb, S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
+        if (S.line_search == 2 || S.line_search == 3) {
+            const double tf = S.line_search == 2
+                                  ? theta_full(kb, S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA)
+                                  : theta_wolfe(th, d1, S.max_halvings, &j, S.a, b, cc, beta, SAB, SACA, SBB, SCAB,
+                                                SCACA);
             double sf, cf;
             sincos(tf, &sf, &cf);
             const double e = delta_energy(cf, sf, S.a, b, cc, beta, SAB, SACA, SBB, SCAB, SCACA);
-            if (e < 0.0) {
+            if (tf >= 0.0 && (S.line_search == 3 || e < 0.0)) {
                 acc_t = tf;
                 dE = e;
                 c = cf;

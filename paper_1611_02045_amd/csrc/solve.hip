@@ -505,8 +505,8 @@ int validate_opts(const gpe_pcg_opts_t* o) {
     if (o->max_iter < 0) { set_error("max_iter must be >= 0"); return GPE_EINVAL; }
     if (o->precision != 0 && o->precision != 1) { set_error("precision must be 0 (FP64) or 1 (mixed)"); return GPE_EINVAL; }
     if (o->beta_rule != 0 && o->beta_rule != 1) { set_error("beta_rule must be 0 (PR) or 1 (FR)"); return GPE_EINVAL; }
-    if (o->line_search < 0 || o->line_search > 2) {
-        set_error("line_search must be 0 (decrease test), 1 (Armijo) or 2 (full)");
+    if (o->line_search < 0 || o->line_search > 3) {
+        set_error("line_search must be 0 (decrease test), 1 (Armijo), 2 (full) or 3 (strong Wolfe)");
         return GPE_EINVAL;
     }
     if (o->max_halvings < 0 || o->max_halvings > 60) { set_error("max_halvings must be in [0, 60]"); return GPE_EINVAL; }

@@ -144,7 +144,7 @@ def default_opts(**kw) -> PcgOpts:
         if k == "beta_rule" and isinstance(v, str):
             v = {"pr": 0, "fr": 1}[v]
         if k == "line_search" and isinstance(v, str):
-            v = {"heuristic": 0, "armijo": 1, "full": 2}[v]
+            v = {"heuristic": 0, "armijo": 1, "full": 2, "wolfe": 3}[v]
         if not hasattr(o, k):
             raise TypeError(f"unknown solver option {k!r}")
         setattr(o, k, v)

@@ -106,13 +106,14 @@ def test_line_search_option(gpe):
     """The step control defaults to the decrease test; the names map to the header's codes and an
     unknown code is refused before any device call."""
     assert gpe.default_opts().line_search == 0
-    assert [gpe.default_opts(line_search=k).line_search for k in ("heuristic", "armijo", "full")] == [0, 1, 2]
+    assert [gpe.default_opts(line_search=k).line_search
+            for k in ("heuristic", "armijo", "full", "wolfe")] == [0, 1, 2, 3]
     assert gpe.default_opts(beta_rule="fr").beta_rule == 1
     L = gpe.lib()
     P = (gpe.Problem * 1)(gpe.make_problem(2, (64, 64), (8.0, 8.0), 10.0, 0.3))
     ptrs = (ctypes.c_void_p * 1)(1)  # never dereferenced: validation fails first
     rep = (gpe.PcgReport * 1)()
-    for bad in (-1, 3):
+    for bad in (-1, 4):
         o = gpe.default_opts()
         o.line_search = bad
         assert L.gpe_pcg_solve_batched(1, P, 0, ptrs, ptrs, ctypes.byref(o), rep, None) == -1

@@ -119,12 +119,12 @@ def test_methods_and_preconditioners(torch_gpu, method, precond):
 
 
 @pytest.mark.parametrize("key", ["1d", "2d", "3d"])
-@pytest.mark.parametrize("line_search,beta_rule", [("armijo", "pr"), ("full", "pr"), ("heuristic", "fr"),
-                                                   ("full", "fr")])
+@pytest.mark.parametrize("line_search,beta_rule", [("armijo", "pr"), ("full", "pr"), ("wolfe", "pr"),
+                                                   ("heuristic", "fr"), ("full", "fr"), ("wolfe", "fr")])
 def test_step_rules_trajectory_matches_oracle(torch_gpu, key, line_search, beta_rule):
-    """The Armijo test, the full line search and the Fletcher-Reeves coefficient: the first
-    iterations agree with the oracle's (energy, chemical potential, residual, accepted angle,
-    halvings)."""
+    """The Armijo test, the full and the strong Wolfe line searches and the Fletcher-Reeves
+    coefficient: the first iterations agree with the oracle's (energy, chemical potential,
+    residual, accepted angle, halvings or evaluations)."""
     prob, V, phi0 = _inputs(key)
     print(f"step rules {key} {line_search} {beta_rule}", flush=True)
     ref = O.pcg(prob, V, phi0, tol_res=1e-30, max_iter=12, record=True, line_search=line_search,
@@ -143,7 +143,7 @@ def test_step_rules_trajectory_matches_oracle(torch_gpu, key, line_search, beta_
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("line_search", ["armijo", "full"])
+@pytest.mark.parametrize("line_search", ["armijo", "full", "wolfe"])
 def test_step_rules_converge_to_oracle_state(torch_gpu, precision, line_search):
     prob, V, phi0 = _inputs("2d")
     tol = 1e-9
