@@ -158,7 +158,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the 64-instance sweep")
     ap.add_argument("--no-configs", action="store_true", help="skip the 1-D, 2-D 256^2 and 3-D single solves")
     ap.add_argument("--no-step-rules", action="store_true",
-                    help="skip the Armijo / full line search / Fletcher-Reeves solves")
+                    help="skip the Armijo / full / Wolfe line search and Fletcher-Reeves solves")
     ap.add_argument("--tol-coarse", type=float, default=1e-5, help="residual tolerance of the coarse nested grids")
     ap.add_argument("--profile-iters", type=int, default=30)
     ap.add_argument("--profile-only", action="store_true",
@@ -237,6 +237,7 @@ def main():
     if not args.no_step_rules:
         step_rules = {"heuristic_pr": {"s": mean(t_mixed), "iters": [r["iters"] for r in reps_mixed]}}
         for tag, extra in (("armijo_pr", {"line_search": "armijo"}), ("full_pr", {"line_search": "full"}),
+                           ("wolfe_pr", {"line_search": "wolfe"}),
                            ("heuristic_fr", {"beta_rule": "fr", "max_iter": 40000})):
             sec, reps = step({**mixed, **extra})
             step_rules[tag] = {"s": sec, "iters": [r["iters"] for r in reps],
