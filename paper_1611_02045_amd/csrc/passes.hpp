@@ -16,6 +16,8 @@
 // points strided along the line.
 #pragma once
 
+#include <type_traits>
+
 #include "fft.hpp"
 
 namespace gpe {
@@ -180,6 +182,19 @@ struct IntakeOf<Op, true> {
     using type = typename Op::Intake;
 };
 
+// Whether launches of an Op run without the occupancy cap (see pass_kernel): Op::WIDE, and for the
+// run-time-size transform (LG = 0) Op::WIDE_RT when the Op defines it.
+template <class Op, class = void>
+struct WideRt {
+    static constexpr bool value = Op::WIDE;
+};
+template <class Op>
+struct WideRt<Op, std::void_t<decltype(Op::WIDE_RT)>> {
+    static constexpr bool value = Op::WIDE_RT;
+};
+template <class Op, int LG>
+constexpr bool kWideAt = LG == 0 ? WideRt<Op>::value : Op::WIDE;
+
 // Twiddles per thread fetched into registers ahead of the scalar logic (more go straight to LDS).
 constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 
@@ -202,11 +217,12 @@ constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 // Launches with several workgroups per CU (!EARLY) ask the register allocator for the occupancy
 // the LDS footprint allows: four 4-wave workgroups per CU for 8-byte points, three for 16-byte
 // points (their line buffers take about 45 KB of the 160 KB).  A WIDE Op keeps more live state than
-// that budget and would spill, so it is left unconstrained.
+// that budget and would spill, so it is left unconstrained (WIDE_RT: only with the run-time-size
+// transform, whose index arithmetic needs more registers).
 // LG > 0: the kernel is specialised for lines of 2^LG points (g.lg[AX] == LG), so the transform's
 // stages, strides and LDS offsets are compile-time constants; LG = 0 takes the size at run time.
 template <typename T, int AX, class Op, int MAXT, bool EARLY, int LG>
-__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(EARLY || Op::WIDE ? 1 : (sizeof(T) == 4 ? 4 : 3))))
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(EARLY || kWideAt<Op, LG> ? 1 : (sizeof(T) == 4 ? 4 : 3))))
 void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op, Partials pr) {
     extern __shared__ double4 smem_raw[];
     int blk_in_inst;

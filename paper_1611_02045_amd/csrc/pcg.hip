@@ -615,8 +615,11 @@ using IntakeA = IntakeAbsorb<A_K, kARowsPerThread>;
 template <typename T, bool ONE>
 struct OpResid {
     // FP32 2-D/3-D: capped at four workgroups per CU despite a small spill (measured faster than the
-    // second round of workgroups the unconstrained allocation leaves on the batched 512^2 step)
+    // second round of workgroups the unconstrained allocation leaves on the batched 512^2 step);
+    // the run-time-size transform would spill 208 bytes under the cap and runs unconstrained
+    // (measured 15% faster on 640^2)
     static constexpr bool FWD = true, INV = ONE, SCALARS = true, PREFETCH = true, WIDE = sizeof(T) == 8 || ONE;
+    static constexpr bool WIDE_RT = true;
     static constexpr int K = A_K;
     static constexpr unsigned MAXMASK = A_MAXMASK;
     IterFields<T> f;
