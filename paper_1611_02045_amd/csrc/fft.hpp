@@ -229,12 +229,14 @@ __device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>*
     }
 }
 
-// fft_line for a compile-time size 2^LG: the same stages, with every stride, offset and stage
-// count a constant (LDS addresses become immediate offsets).  WAVE: lines lie within one wave.
-template <typename T, int DIR, int LG, bool WAVE>
+// fft_line for a compile-time size 2^LG (F5: 5 * 2^LG): the same stages, with every stride, offset
+// and stage count a constant (LDS addresses become immediate offsets).  WAVE: lines lie within one
+// wave.
+template <typename T, int DIR, int LG, bool WAVE, bool F5 = false>
 __device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, int t) {
     static_assert(LG >= 3 && LG <= 10, "lines of 8 to 1024 points");
-    constexpr int TPL = 1 << (LG - 3);
+    static_assert(!F5 || (LG <= 7 && !WAVE), "lines of 5 * 2^LG points: at most 640, across waves");
+    constexpr int TPL = F5 ? 5 << (LG - 3) : 1 << (LG - 3);
     constexpr int REM = LG % 3;
     constexpr int N8 = LG / 3;
     auto sync = [] {
@@ -272,7 +274,7 @@ __device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<
         const int Ns = 1 << lgNs;
         if (lgNs > 0) {
             const int jm = t & (Ns - 1);
-            const int step = jm << (LG - 3 - lgNs);
+            const int step = jm * (TPL >> lgNs);  // jm * M / (8 Ns)
             C2<T> w1 = tw[step], w2 = tw[2 * step], w4 = tw[4 * step];
             if (DIR > 0) {
                 w1.y = -w1.y;
@@ -289,12 +291,36 @@ __device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<
             v[7] = mul(v[7], mul(w3, w4));
         }
         dft8<T, DIR>(v);
-        if (k + 1 < N8) {
+        if (k + 1 < N8 || F5) {
             const int base = ((t >> lgNs) << (lgNs + 3)) + (t & (Ns - 1));
 #pragma unroll
             for (int r = 0; r < 8; ++r) buf[lpad(base + r * Ns)] = v[r];
-            read_back();
+            if (k + 1 < N8) read_back();
         }
+    }
+    if constexpr (F5) {
+        // radix-5 stage at Ns = P = 2^LG (see fft_line): butterflies j = t + q TPL < P
+        constexpr int P = 1 << LG;
+        sync();
+#pragma unroll
+        for (int q = 0; q < (P + TPL - 1) / TPL; ++q) {
+            const int j = t + q * TPL;
+            if (j < P) {
+                C2<T> x[5];
+#pragma unroll
+                for (int r = 0; r < 5; ++r) x[r] = buf[lpad(j + r * P)];
+#pragma unroll
+                for (int r = 1; r < 5; ++r) {
+                    C2<T> w = tw[j * r];
+                    if (DIR > 0) w.y = -w.y;
+                    x[r] = mul(x[r], w);
+                }
+                dft5<T, DIR>(x[0], x[1], x[2], x[3], x[4]);
+#pragma unroll
+                for (int r = 0; r < 5; ++r) buf[lpad(j + r * P)] = x[r];
+            }
+        }
+        read_back();
     }
 }
 

@@ -42,6 +42,12 @@ __host__ __device__ inline int64_t lines_per_field(const Geo& g, int AX) {
     return g.N / g.n[AX];
 }
 
+// Compile-time line sizes of the pass kernels: LG in 1..10 stands for 2^LG points, LG >= 100 for
+// 5 * 2^(LG - 100) points; 0 means the size is taken at run time.
+__host__ __device__ constexpr bool ct_f5(int LG) { return LG >= 100; }
+__host__ __device__ constexpr int ct_lg(int LG) { return LG >= 100 ? LG - 100 : LG; }
+__host__ __device__ constexpr int ct_points(int LG) { return ct_f5(LG) ? 5 << ct_lg(LG) : 1 << ct_lg(LG); }
+
 // When every extent is a power of two the decomposition of the launch into lines uses shifts and
 // masks only (64-bit integer division is a long software sequence on the GPU); grids with an axis
 // of 5 * 2^k points take 32-bit divisions (line counts stay far below 2^32).  blk receives the
@@ -49,8 +55,8 @@ __host__ __device__ inline int64_t lines_per_field(const Geo& g, int AX) {
 template <int AX, int LG = 0>
 __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
     LineCtx lc;
-    lc.lg = LG > 0 ? LG : g.lg[AX];  // a compile-time size folds every index below
-    const bool f5 = LG == 0 && g.f5[AX];
+    lc.lg = LG > 0 ? ct_lg(LG) : g.lg[AX];  // a compile-time size folds every index below
+    const bool f5 = LG > 0 ? ct_f5(LG) : g.f5[AX] != 0;
     lc.M = f5 ? 5 << lc.lg : 1 << lc.lg;
     lc.TPL = lc.M >> 3;
     // x lines take consecutive lanes, TPL of them per line; lines of 5 * 2^k points can straddle
@@ -127,7 +133,7 @@ __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
 template <typename T, int DIR, int AX, int LG>
 __device__ __forceinline__ void line_fft(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, const LineCtx& lc) {
     if constexpr (LG > 0)
-        fft_line_ct<T, DIR, LG, AX == 0 && LG <= 9>(v, buf, tw, lc.t);
+        fft_line_ct<T, DIR, ct_lg(LG), AX == 0 && !ct_f5(LG) && ct_lg(LG) <= 9, ct_f5(LG)>(v, buf, tw, lc.t);
     else
         fft_line<T, DIR>(v, buf, tw, lc.t, lc.lg, lc.M, lc.wave);
 }
@@ -193,7 +199,7 @@ struct WideRt<Op, std::void_t<decltype(Op::WIDE_RT)>> {
     static constexpr bool value = Op::WIDE_RT;
 };
 template <class Op, int LG>
-constexpr bool kWideAt = LG == 0 ? WideRt<Op>::value : Op::WIDE;
+constexpr bool kWideAt = LG == 0 || ct_f5(LG) ? WideRt<Op>::value : Op::WIDE;
 
 // Twiddles per thread fetched into registers ahead of the scalar logic (more go straight to LDS).
 constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
@@ -219,8 +225,9 @@ constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 // points (their line buffers take about 45 KB of the 160 KB).  A WIDE Op keeps more live state than
 // that budget and would spill, so it is left unconstrained (WIDE_RT: only with the run-time-size
 // transform, whose index arithmetic needs more registers).
-// LG > 0: the kernel is specialised for lines of 2^LG points (g.lg[AX] == LG), so the transform's
-// stages, strides and LDS offsets are compile-time constants; LG = 0 takes the size at run time.
+// LG > 0: the kernel is specialised for lines of ct_points(LG) points (2^LG, or 5 * 2^(LG - 100)
+// for LG >= 100), so the transform's stages, strides and LDS offsets are compile-time constants;
+// LG = 0 takes the size at run time.
 template <typename T, int AX, class Op, int MAXT, bool EARLY, int LG>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(EARLY || kWideAt<Op, LG> ? 1 : (sizeof(T) == 4 ? 4 : 3))))
 void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op, Partials pr) {
