@@ -97,16 +97,18 @@ def _levels(m0, nlev, L, beta, omega):
 
 
 @pytest.mark.parametrize("precision,tol_E", [("fp64", 1e-10), ("mixed", 1e-6)])
-def test_nested_solve_matches_oracle(torch_gpu, precision, tol_E):
-    """16^2 -> 32^2 -> 64^2 at beta = 100, Omega = 0.4 from start (d): every level converges and the
-    finest state has the oracle's nested-solve energy and density."""
+@pytest.mark.parametrize("coarsest", [16, 40])
+def test_nested_solve_matches_oracle(torch_gpu, precision, tol_E, coarsest):
+    """16^2 -> 32^2 -> 64^2 (and 40^2 -> 80^2 -> 160^2, the 5 * 2^k hierarchy of the paper's 640
+    grids) at beta = 100, Omega = 0.4 from start (d): every level converges and the finest state has
+    the oracle's nested-solve energy and density."""
     from paper_1611_02045_amd import gpe
     torch = torch_gpu
-    probs, Vs = _levels(16, 3, 8.0, 100.0, 0.4)
+    probs, Vs = _levels(coarsest, 3, 8.0, 100.0, 0.4)
     start = paper_initial(probs[0], "d", 0.4)
     ref, ref_levels = O.pcg_nested(probs, Vs, start, tol_coarse=1e-6, tol_res=1e-9, max_iter=5000)
     assert ref.status == "converged"
-    print(f"nested {precision}", flush=True)
+    print(f"nested {precision} from {coarsest}^2", flush=True)
     st, outs, reps = gpe.pcg_solve_nested([probs[0]], [[_to(torch, V, "f64")] for V in Vs], [_to(torch, start, "f64")],
                                           "f64", tol_coarse=1e-6, tol=1e-9, max_iter=5000, precision=precision)
     assert st == 0
