@@ -204,6 +204,52 @@ def test_nonfinite_input_is_reported(torch_gpu):
     assert ei.value.status == -4
 
 
+def test_zero_start_is_reported_not_iterated(torch_gpu):
+    """A start with no norm cannot be normalised: the solve ends with GPE_ENONFINITE at once (no
+    iteration runs on the NaN field)."""
+    from paper_1611_02045_amd import gpe
+    prob, V, phi0 = _inputs("2d")
+    print("zero start", flush=True)
+    with pytest.raises(gpe.GpeError) as ei:
+        _gpu_solve(torch_gpu, prob, V, np.zeros_like(phi0))
+    assert ei.value.status == -4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_start_at_the_ground_state_takes_no_iteration(torch_gpu, precision):
+    """beta = 0, harmonic trap in 2-D: the Gaussian start is already the discrete ground state to
+    spectral accuracy (E = 1/2 per axis), so in FP64 the convergence test passes at n = 0 and the
+    field comes back unchanged; in mixed precision the start is rounded to FP32 first, and the FP64
+    phase restores the state in a few iterations."""
+    from gpe_inputs import gaussian
+    prob = Problem(2, (64, 64), (8.0, 8.0), 0.0, 0.0)
+    V = harmonic_potential(prob)
+    phi0 = gaussian(prob)
+    print(f"ground-state start {precision}", flush=True)
+    rep, phi, _ = _gpu_solve(torch_gpu, prob, V, phi0, tol_res=1e-8, precision=precision)
+    assert rep["status"] == 0
+    assert abs(rep["E"] - 1.0) < 1e-10
+    if precision == "fp64":
+        assert rep["iters"] == 0
+        np.testing.assert_allclose(phi, phi0, atol=1e-13)
+    else:
+        assert rep["iters"] <= 50
+        np.testing.assert_allclose(np.abs(phi), np.abs(phi0), atol=1e-7)
+
+
+def test_zero_max_iter_reports_the_start(torch_gpu):
+    """max_iter = 0: no step is taken; the report carries the start's energy and residual."""
+    prob, V, phi0 = _inputs("2d")
+    print("max_iter 0", flush=True)
+    rep, phi, _ = _gpu_solve(torch_gpu, prob, V, phi0, tol_res=1e-12, max_iter=0)
+    assert rep["status"] == 1 and rep["iters"] == 0
+    unit = phi0 / O.norm(prob, phi0)
+    np.testing.assert_allclose(phi, unit, atol=1e-13)
+    assert abs(rep["E"] - O.energy(prob, V, unit)) < 1e-11 * abs(rep["E"])
+    r, _ = O.residual(prob, V, unit)
+    assert abs(rep["res_inf"] - np.max(np.abs(r))) < 1e-9 * np.max(np.abs(r))
+
+
 def test_trajectory_large_grid_collapsed_partials(torch_gpu):
     """1024^2 (512 partial rows per pass, reduced through the one-row collapse): the first
     iterations agree with the oracle."""
