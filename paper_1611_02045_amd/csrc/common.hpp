@@ -41,6 +41,8 @@ struct Geo {
     int lg[3];      // log2 of the power-of-two part of n (n = 2^lg, or 5 * 2^lg when f5)
     int f5[3];      // 1 when n = 5 * 2^lg (a radix-5 stage ends the line transform)
     int pow2;       // every axis is a power of two (the line decomposition uses shifts only)
+    int b0, bl;     // a launch covers instances [b0, b0 + bl) of the B laid out (bl = 0: all of them);
+                    // tiles and partial-row strides always follow the full B
     double L[3];    // half-widths
     double h[3];    // spacings 2L/n
     double dk[3];   // frequency spacings pi/L

@@ -131,7 +131,7 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
     // reduction scratch sized for the pass's own sums and for absorbing up to 16 sums of its predecessor
     const size_t lds = pass_lds_bytes<T>(g.n[AX], C, threads, Op::K > 16 ? Op::K : 16, AX);
     if (threads > kMaxPassThreads) return hipErrorInvalidConfiguration;
-    const int64_t blocks = nb * (int64_t)B;
+    const int64_t blocks = nb * (int64_t)(g.bl > 0 ? g.bl : B);  // instances [g.b0, g.b0 + g.bl) only
     // one workgroup per CU or fewer: fetch everything ahead of the scalar logic (see pass_kernel)
     const bool early = blocks <= device_cus();
     // lines of 128, 256, 512 and 640 points (the common sizes and the paper's) take the compile-time

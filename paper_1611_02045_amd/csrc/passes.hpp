@@ -85,8 +85,9 @@ __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
     if (!g.pow2) {
         const unsigned lpf = (unsigned)(g.N / lc.M);
         const unsigned line = (grp << lgC) + (unsigned)lc.c;
-        lc.b = (int)(line / lpf);
-        const unsigned lf = line - (unsigned)lc.b * lpf;
+        const unsigned bi = line / lpf;  // instance within the launch
+        lc.b = g.b0 + (int)bi;
+        const unsigned lf = line - bi * lpf;
         blk = (int)(lf >> lgC);
         lc.off_b = (int64_t)lc.b * g.N;
         const unsigned q = lf / (unsigned)(AX == 0 ? ny : nx);
@@ -106,7 +107,7 @@ __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
         return lc;
     }
     const int64_t line = ((int64_t)grp << lgC) + lc.c;
-    lc.b = (int)(line >> lg_lpf);
+    lc.b = g.b0 + (int)(line >> lg_lpf);
     const int64_t lf = line & (((int64_t)1 << lg_lpf) - 1);
     blk = (int)(lf >> lgC);
     lc.off_b = (int64_t)lc.b * g.N;

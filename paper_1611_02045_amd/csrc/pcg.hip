@@ -979,11 +979,12 @@ struct OpLp {
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, const Scal* Sin, Scal* Sout, int64_t N, int nbpi,
-                                                   int pre, Partials pb, Partials pr) {
+                                                   int pre, Partials pb, Partials pr, int b0) {
     __shared__ double red[(256 / 64 + 1) * 16 + 8];
     __shared__ Scal s;
-    const int b = blockIdx.x / nbpi;
-    const int blk = blockIdx.x - b * nbpi;
+    const int bi = blockIdx.x / nbpi;  // instance within the launch
+    const int b = b0 + bi;
+    const int blk = blockIdx.x - bi * nbpi;
     IntakeStep it;
     intake_step(Sin, pb, b, it);
     begin_step(Sin, Sout, pb, b, blk, red, &s, it);
@@ -1019,10 +1020,11 @@ __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, const Scal*
 // fixed order), so that the consuming pass's workgroups reduce a single row.
 // ---------------------------------------------------------------------------------------------
 template <int K>
-__global__ __launch_bounds__(256) void k_collapse(const double* parts, int nb, int stride, double* out, unsigned mask) {
+__global__ __launch_bounds__(256) void k_collapse(const double* parts, int nb, int stride, double* out, unsigned mask,
+                                                 int b0) {
     __shared__ double red[(256 / 64 + 1) * K];
     __shared__ double tot[K];
-    const int b = blockIdx.x;
+    const int b = b0 + blockIdx.x;
     reduce_partials<K>(parts + (size_t)b * stride * K, nb, red, tot, mask);
     for (int k = threadIdx.x; k < K; k += blockDim.x) out[(size_t)b * K + k] = tot[k];
 }
@@ -1039,6 +1041,8 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     Scal* S_step = c.S;
     Scal* S_res = c.S + c.B;
     Scal* S_dir = c.S + 2 * c.B;
+    // launched instances: [g.b0, g.b0 + Bl) (converged instances outside the range are not launched)
+    const int Bl = g.bl > 0 ? g.bl : c.B;
     hipError_t e;
     auto region = [&](int r, int ax) {
         const int nb = pass_blocks_per_field(g, ax, cb, c.B, true);
@@ -1049,11 +1053,11 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         if (p.nb <= kAbsorbRows) return p;
         const Partials q{c.parts + (size_t)rc * c.region_doubles, 1, 1, 0};
         if (K == A_K)
-            hipLaunchKernelGGL(k_collapse<A_K>, dim3((unsigned)c.B), dim3(256), 0, s, p.parts, p.nb, p.row_stride(),
-                               q.parts, mask);
+            hipLaunchKernelGGL(k_collapse<A_K>, dim3((unsigned)Bl), dim3(256), 0, s, p.parts, p.nb, p.row_stride(),
+                               q.parts, mask, g.b0);
         else
-            hipLaunchKernelGGL(k_collapse<B_K>, dim3((unsigned)c.B), dim3(256), 0, s, p.parts, p.nb, p.row_stride(),
-                               q.parts, mask);
+            hipLaunchKernelGGL(k_collapse<B_K>, dim3((unsigned)Bl), dim3(256), 0, s, p.parts, p.nb, p.row_stride(),
+                               q.parts, mask, g.b0);
         return q;
     };
     const Partials none{nullptr, 0, 0, 0};
@@ -1086,8 +1090,8 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         // diagonal P (identity or P_V): one pointwise kernel for residual, P r and every sum
         const int nbpi = c.pointwise_blocks;
         const Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, nbpi, nbpi, 0};
-        launch_timed(tick("step_resid_diag", 21), k_resid_diag<T>, dim3((unsigned)(nbpi * c.B)), dim3(256), 0, s, f,
-                     S_dir, S_step, g.N, nbpi, pre, sb, pr);
+        launch_timed(tick("step_resid_diag", 21), k_resid_diag<T>, dim3((unsigned)(nbpi * Bl)), dim3(256), 0, s, f,
+                     S_dir, S_step, g.N, nbpi, pre, sb, pr, g.b0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         pres = consumable(pr, R_A1C, A_K, A_MAXMASK);
         pdir = pres;

@@ -258,6 +258,10 @@ struct GraphExec {
         if (e != hipSuccess) exec = nullptr;
         return e;
     }
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+    }
     ~GraphExec() {
         if (exec) (void)hipGraphExecDestroy(exec);
     }
@@ -351,6 +355,21 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
         bool all_done = true;
         for (int b = 0; b < B; ++b) all_done = all_done && host_S[b].done;
         if (all_done) break;
+        // Converged instances at either end of the launched range are left out of later launches
+        // (a masked instance still costs its workgroups' state and row reads in every pass); the
+        // tiles and row layout keep following all B instances.  The stream is idle here, so the
+        // graph holding the old range can go; the next chunk captures the new one.
+        {
+            int first = 0, last = B - 1;
+            while (host_S[first].done) ++first;
+            while (host_S[last].done) --last;
+            const int nl = last - first + 1;
+            if (first != c.g.b0 || nl != (c.g.bl > 0 ? c.g.bl : B)) {
+                c.g.b0 = first;
+                c.g.bl = nl;
+                graph.reset();
+            }
+        }
         // Every queued iteration of an unfinished instance ran, so r/rp roles are in sync.
         if (pa.refresh_every > 0 && since_refresh >= pa.refresh_every) {
             since_refresh = 0;
