@@ -21,7 +21,7 @@ pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 # Transforms and derivatives
 # ----------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("M,L", [(16, 3.0), (32, 8.0), (64, 16.0)])
+@pytest.mark.parametrize("M,L", [(16, 3.0), (32, 8.0), (64, 16.0), (40, 5.0), (80, 10.0)])
 def test_derivatives_of_plane_waves_are_exact(M, L):
     """e^{i xi_p (x + L)} is an exact eigenfunction of [[d]] (eigenvalue i xi_p) and [[d^2]]
     (eigenvalue -xi_p^2) for every p in [-M/2, M/2 - 1], Nyquist included (kept as written)."""
@@ -47,10 +47,12 @@ def _naive_derivative(M, L, f_line, power):
     return out / M
 
 
-def test_directional_operators_match_brute_force_sums():
+@pytest.mark.parametrize("n", [(8, 6), (40, 10)])
+def test_directional_operators_match_brute_force_sums(n):
     """[[d^2_x]], [[d^2_y]], x[[d_y]], y[[d_x]] and L_z on a random 2-D field against the explicit
-    sums of Section 3 (distinct sizes and half-widths per axis to catch transposed axes)."""
-    prob = Problem(2, (8, 6), (3.0, 2.0), 0.0, 0.0)
+    sums of Section 3 (distinct sizes and half-widths per axis to catch transposed axes; sizes with a
+    factor 5 as on the paper's 640-point grids)."""
+    prob = Problem(2, n, (3.0, 2.0), 0.0, 0.0)
     f = random_field(prob, 7)
     x, y = mesh(prob)
     nx, ny = prob.n
