@@ -157,6 +157,7 @@ def main():
     ap.add_argument("--no-nested", action="store_true", help="skip the nested-grid solves")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 64-instance sweep")
     ap.add_argument("--no-configs", action="store_true", help="skip the 1-D, 2-D 256^2 and 3-D single solves")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-step-rules", action="store_true",
                     help="skip the Armijo / full / Wolfe line search and Fletcher-Reeves solves")
     ap.add_argument("--tol-coarse", type=float, default=1e-5, help="residual tolerance of the coarse nested grids")
@@ -357,6 +358,50 @@ def main():
         for k, v in configs.items():
             log(f"[bench] config {k}: {v['s']:.4f} s, {v['iters']} iterations, E = {v['E']:.10f}, {v['status']}")
 
+    # the differentiation workload (2-D 256^2 on [-16, 16]^2, beta = 1000, Omega = 0.85, harmonic trap
+    # with 9 Gaussian pins): loss = E(phi*) + h^2 sum (|phi*|^2 - rho_t)^2, rho_t from a solve at the
+    # seeded target parameters; forward = the FP64 ground-state solve to 1e-11, backward = the implicit
+    # adjoint solve and the parameter gradients (gamma_y, A, beta, Omega) through torch autograd
+    diff = None
+    if not args.no_diff:
+        import numpy as np
+        from gpe_inputs import differentiation_workload, mesh, target_parameters
+        from paper_1611_02045_amd.autograd import Grid, energy as energy_fn, ground_state
+        dprob, cent, _, dphi0 = differentiation_workload()
+        dgrid = Grid(2, dprob.n, dprob.L)
+        x, y = mesh(dprob)
+        X = torch.from_numpy(np.broadcast_to(x, dprob.shape).copy()).to("cuda")
+        Y = torch.from_numpy(np.broadcast_to(y, dprob.shape).copy()).to("cuda")
+        Cc = torch.tensor(cent, device="cuda")
+        f64 = dict(dtype=torch.float64, device="cuda")
+
+        def pinned(gy, A):
+            Vp = 0.5 * (X ** 2 + gy ** 2 * Y ** 2)
+            for j in range(Cc.shape[0]):
+                Vp = Vp + A * torch.exp(-((X - Cc[j, 0]) ** 2 + (Y - Cc[j, 1]) ** 2) / (2 * 0.5 ** 2))
+            return Vp
+
+        gy_t, A_t = target_parameters()
+        phi_t = torch.from_numpy(dphi0).to("cuda")
+        gpe.Plan.from_problem(dprob, "f64").pcg_solve(pinned(torch.tensor(gy_t, **f64), torch.tensor(A_t, **f64))
+                                                      .contiguous(), phi_t, tol=1e-10, max_iter=200000)
+        rho_t = (phi_t.abs() ** 2).detach()
+        theta = [torch.tensor(v, requires_grad=True, **f64) for v in (1.05, 2.0, dprob.beta, dprob.omega)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Vt = pinned(theta[0], theta[1])
+        phis = ground_state(Vt, theta[2], theta[3], torch.from_numpy(dphi0).to("cuda"), dgrid)
+        loss = energy_fn(phis, Vt, theta[2], theta[3], dgrid) + dgrid.cell * torch.sum((phis.abs() ** 2 - rho_t) ** 2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        diff = {"workload": "2-D 256^2, beta=1000, Omega=0.85, 9 pins; d loss / d(gamma_y, A, beta, Omega)",
+                "forward_s": t1 - t0, "backward_s": t2 - t1, "loss": float(loss.item()),
+                "grad": [float(t.grad.item()) for t in theta]}
+        log(f"[bench] differentiation: forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s, grad {diff['grad']}")
+
     # H_phi applies/s (single field and a batch of 32 fields, FP64 and FP32)
     log("[bench] H applies")
     plan64 = gpe.Plan.from_problem(prob, "f64")
@@ -441,6 +486,7 @@ def main():
         "iters_fp64": it_fp64,
         "single_start": single,
         "step_rules": step_rules,
+        "differentiation": diff,
         "nested_grids": nested,
         "sweep_64": sweep,
         "other_configs": configs,
