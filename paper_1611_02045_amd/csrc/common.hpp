@@ -41,8 +41,10 @@ struct Geo {
     int lg[3];      // log2 of the power-of-two part of n (n = 2^lg, or 5 * 2^lg when f5)
     int f5[3];      // 1 when n = 5 * 2^lg (a radix-5 stage ends the line transform)
     int pow2;       // every axis is a power of two (the line decomposition uses shifts only)
-    int b0, bl;     // a launch covers instances [b0, b0 + bl) of the B laid out (bl = 0: all of them);
-                    // tiles and partial-row strides always follow the full B
+    int b0, bl;     // a launch covers instances [b0, b0 + bl) of the B laid out (bl = 0: all of them),
+                    // or, when imap is set, the bl instances imap[0 .. bl) (device, each < B); tiles and
+                    // partial-row strides always follow the full B
+    const int* imap;
     double L[3];    // half-widths
     double h[3];    // spacings 2L/n
     double dk[3];   // frequency spacings pi/L

@@ -86,7 +86,7 @@ __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
         const unsigned lpf = (unsigned)(g.N / lc.M);
         const unsigned line = (grp << lgC) + (unsigned)lc.c;
         const unsigned bi = line / lpf;  // instance within the launch
-        lc.b = g.b0 + (int)bi;
+        lc.b = g.imap ? g.imap[bi] : g.b0 + (int)bi;
         const unsigned lf = line - bi * lpf;
         blk = (int)(lf >> lgC);
         lc.off_b = (int64_t)lc.b * g.N;
@@ -107,7 +107,7 @@ __device__ __forceinline__ LineCtx decode_line(const Geo& g, int C, int& blk) {
         return lc;
     }
     const int64_t line = ((int64_t)grp << lgC) + lc.c;
-    lc.b = g.b0 + (int)(line >> lg_lpf);
+    lc.b = g.imap ? g.imap[line >> lg_lpf] : g.b0 + (int)(line >> lg_lpf);
     const int64_t lf = line & (((int64_t)1 << lg_lpf) - 1);
     blk = (int)(lf >> lgC);
     lc.off_b = (int64_t)lc.b * g.N;

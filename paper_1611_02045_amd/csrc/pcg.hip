@@ -979,11 +979,11 @@ struct OpLp {
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, const Scal* Sin, Scal* Sout, int64_t N, int nbpi,
-                                                   int pre, Partials pb, Partials pr, int b0) {
+                                                   int pre, Partials pb, Partials pr, int b0, const int* imap) {
     __shared__ double red[(256 / 64 + 1) * 16 + 8];
     __shared__ Scal s;
     const int bi = blockIdx.x / nbpi;  // instance within the launch
-    const int b = b0 + bi;
+    const int b = imap ? imap[bi] : b0 + bi;
     const int blk = blockIdx.x - bi * nbpi;
     IntakeStep it;
     intake_step(Sin, pb, b, it);
@@ -1021,10 +1021,10 @@ __global__ __launch_bounds__(256) void k_resid_diag(IterFields<T> f, const Scal*
 // ---------------------------------------------------------------------------------------------
 template <int K>
 __global__ __launch_bounds__(256) void k_collapse(const double* parts, int nb, int stride, double* out, unsigned mask,
-                                                 int b0) {
+                                                 int b0, const int* imap) {
     __shared__ double red[(256 / 64 + 1) * K];
     __shared__ double tot[K];
-    const int b = b0 + blockIdx.x;
+    const int b = imap ? imap[blockIdx.x] : b0 + (int)blockIdx.x;
     reduce_partials<K>(parts + (size_t)b * stride * K, nb, red, tot, mask);
     for (int k = threadIdx.x; k < K; k += blockDim.x) out[(size_t)b * K + k] = tot[k];
 }
@@ -1041,7 +1041,7 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     Scal* S_step = c.S;
     Scal* S_res = c.S + c.B;
     Scal* S_dir = c.S + 2 * c.B;
-    // launched instances: [g.b0, g.b0 + Bl) (converged instances outside the range are not launched)
+    // launched instances: [g.b0, g.b0 + Bl), or g.imap[0 .. Bl) (converged instances are not launched)
     const int Bl = g.bl > 0 ? g.bl : c.B;
     hipError_t e;
     auto region = [&](int r, int ax) {
@@ -1054,10 +1054,10 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         const Partials q{c.parts + (size_t)rc * c.region_doubles, 1, 1, 0};
         if (K == A_K)
             hipLaunchKernelGGL(k_collapse<A_K>, dim3((unsigned)Bl), dim3(256), 0, s, p.parts, p.nb, p.row_stride(),
-                               q.parts, mask, g.b0);
+                               q.parts, mask, g.b0, g.imap);
         else
             hipLaunchKernelGGL(k_collapse<B_K>, dim3((unsigned)Bl), dim3(256), 0, s, p.parts, p.nb, p.row_stride(),
-                               q.parts, mask, g.b0);
+                               q.parts, mask, g.b0, g.imap);
         return q;
     };
     const Partials none{nullptr, 0, 0, 0};
@@ -1091,7 +1091,7 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
         const int nbpi = c.pointwise_blocks;
         const Partials pr{c.parts + (size_t)R_A1 * c.region_doubles, nbpi, nbpi, 0};
         launch_timed(tick("step_resid_diag", 21), k_resid_diag<T>, dim3((unsigned)(nbpi * Bl)), dim3(256), 0, s, f,
-                     S_dir, S_step, g.N, nbpi, pre, sb, pr, g.b0);
+                     S_dir, S_step, g.N, nbpi, pre, sb, pr, g.b0, g.imap);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         pres = consumable(pr, R_A1C, A_K, A_MAXMASK);
         pdir = pres;

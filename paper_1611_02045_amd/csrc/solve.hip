@@ -324,6 +324,12 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
     // one chunk ran eagerly, the next is captured into a graph and every later chunk replays it.
     GraphExec graph;
     int64_t chunks = 0;
+    // device list of the unfinished instances (used when they are not contiguous), owned by the phase
+    struct OwnedBuf : DevBuf {
+        ~OwnedBuf() { release(); }
+    } imap;
+    std::vector<int> imap_host;
+    if ((e = imap.ensure(sizeof(int) * (size_t)B)) != hipSuccess) return e;
     for (;;) {
         // host-side guard: every queued iteration either advances n or finishes the instance
         if (queued > 2 * max_iter + 4 * (int64_t)pa.check_every + 64) return hipErrorUnknown;
@@ -355,17 +361,32 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
         bool all_done = true;
         for (int b = 0; b < B; ++b) all_done = all_done && host_S[b].done;
         if (all_done) break;
-        // Converged instances at either end of the launched range are left out of later launches
-        // (a masked instance still costs its workgroups' state and row reads in every pass); the
-        // tiles and row layout keep following all B instances.  The stream is idle here, so the
-        // graph holding the old range can go; the next chunk captures the new one.
+        // Converged instances are left out of later launches (a masked instance still costs its
+        // workgroups' state and row reads in every pass): a contiguous run of unfinished instances is
+        // launched as a range, any other set through the device list of their indices.  Tiles and row
+        // layout keep following all B instances.  The stream is idle here, so the list can be
+        // rewritten and the graph holding the old launches can go; the next chunk captures anew.
         {
-            int first = 0, last = B - 1;
-            while (host_S[first].done) ++first;
-            while (host_S[last].done) --last;
-            const int nl = last - first + 1;
-            if (first != c.g.b0 || nl != (c.g.bl > 0 ? c.g.bl : B)) {
-                c.g.b0 = first;
+            std::vector<int> run;
+            for (int b = 0; b < B; ++b)
+                if (!host_S[b].done) run.push_back(b);
+            const int nl = (int)run.size();
+            const bool contiguous = run.back() - run.front() + 1 == nl;
+            const bool same = contiguous ? (!c.g.imap && c.g.b0 == run.front() && (c.g.bl > 0 ? c.g.bl : B) == nl)
+                                         : (c.g.imap && c.g.bl == nl && run == imap_host);
+            if (!same) {
+                if (contiguous) {
+                    c.g.imap = nullptr;
+                    c.g.b0 = run.front();
+                } else {
+                    imap_host = run;
+                    if ((e = hipMemcpyAsync(imap.ptr, imap_host.data(), sizeof(int) * nl, hipMemcpyHostToDevice, s)) !=
+                        hipSuccess)
+                        return e;
+                    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+                    c.g.imap = (const int*)imap.ptr;
+                    c.g.b0 = 0;
+                }
                 c.g.bl = nl;
                 graph.reset();
             }

@@ -133,3 +133,37 @@ def test_batched_profile_counts_every_instance(torch_gpu):
     with pytest.raises(gpe.GpeError) as ei:
         gpe.pcg_profile_batched(odd, oddV, oddphi, "f64", iters=2)
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_converged_instances_inside_a_part_leave_the_launches(torch_gpu, precision):
+    """One grid, six instances [A, G, B, G, C, G] (two parts of three): the G instances (beta = 0,
+    their exact Gaussian ground state as start) finish first, so each part continues
+    with a set of unfinished instances that is not contiguous (launched through a list of indices)
+    or a shorter range.  Every running start gives exactly what it gives solved alone."""
+    from gpe_inputs import gaussian
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    runs = [Problem(2, (64, 64), (8.0, 8.0), b, o) for b, o in ((80.0, 0.3), (150.0, 0.6), (40.0, 0.5))]
+    still = Problem(2, (64, 64), (8.0, 8.0), 0.0, 0.0)
+    probs, Vs, starts = [], [], []
+    for k, p in enumerate(runs):
+        probs += [p, still]
+        Vs += [harmonic_potential(p), harmonic_potential(still)]
+        starts += [vortex_seed_2d(p, 400 + k), gaussian(still)]
+    opts = dict(tol=1e-9, max_iter=5000, precision=precision, check_every=4)
+    print(f"inner converged instances {precision}", flush=True)
+    phis = [torch.from_numpy(s).to("cuda") for s in starts]
+    st, reps = gpe.pcg_solve_batched(probs, [torch.from_numpy(V).to("cuda") for V in Vs], phis, "f64", **opts)
+    assert st == 0, reps
+    for k in range(len(probs)):
+        if k % 2 == 1:
+            # FP64: done at the first test; mixed: a few FP64 iterations restore the FP32-rounded start
+            assert reps[k]["status"] == 0 and reps[k]["iters"] <= (0 if precision == "fp64" else 20)
+            continue
+        plan = gpe.Plan.from_problem(probs[k], "f64")
+        alone = torch.from_numpy(starts[k]).to("cuda")
+        rep = plan.pcg_solve(torch.from_numpy(Vs[k]).to("cuda"), alone, **opts)
+        assert rep["iters"] == reps[k]["iters"] and rep["iters"] > 40
+        assert rep["E"] == reps[k]["E"]
+        assert torch.equal(alone, phis[k])
