@@ -134,18 +134,19 @@ hipError_t launch_pass(const Geo& g, int B, const void* tw, const Op& op, Partia
     const int64_t blocks = nb * (int64_t)(g.bl > 0 ? g.bl : B);  // instances [g.b0, g.b0 + g.bl) only
     // one workgroup per CU or fewer: fetch everything ahead of the scalar logic (see pass_kernel)
     const bool early = blocks <= device_cus();
-    // lines of 128, 256, 512 and 640 points (the common sizes and the paper's) take the compile-time
-    // transform (measured 18% less time per iteration than the run-time one on 256^2); other sizes
-    // the run-time one
+    // lines of 64, 128, 256, 512 and 640 points (the common sizes and the paper's) take the
+    // compile-time transform (measured 18% less time per iteration than the run-time one on 256^2,
+    // 22-27% on 64^2 and 64^3); other sizes the run-time one
     constexpr int kMaxT = kMaxPassThreads;
     const int lg = g.lg[AX];
-    const int ct = g.f5[AX] ? (lg == 7 ? 4 : 0) : (lg == 9 ? 3 : lg == 8 ? 2 : lg == 7 ? 1 : 0);
+    const int ct = g.f5[AX] ? (lg == 7 ? 4 : 0) : (lg == 9 ? 3 : lg == 8 ? 2 : lg == 7 ? 1 : lg == 6 ? 5 : 0);
     using K = decltype(&pass_kernel<T, AX, Op, kMaxT, true, 0>);
-    const K variants[10] = {pass_kernel<T, AX, Op, kMaxT, false, 0>,   pass_kernel<T, AX, Op, kMaxT, true, 0>,
+    const K variants[12] = {pass_kernel<T, AX, Op, kMaxT, false, 0>,   pass_kernel<T, AX, Op, kMaxT, true, 0>,
                             pass_kernel<T, AX, Op, kMaxT, false, 7>,   pass_kernel<T, AX, Op, kMaxT, true, 7>,
                             pass_kernel<T, AX, Op, kMaxT, false, 8>,   pass_kernel<T, AX, Op, kMaxT, true, 8>,
                             pass_kernel<T, AX, Op, kMaxT, false, 9>,   pass_kernel<T, AX, Op, kMaxT, true, 9>,
-                            pass_kernel<T, AX, Op, kMaxT, false, 107>, pass_kernel<T, AX, Op, kMaxT, true, 107>};
+                            pass_kernel<T, AX, Op, kMaxT, false, 107>, pass_kernel<T, AX, Op, kMaxT, true, 107>,
+                            pass_kernel<T, AX, Op, kMaxT, false, 6>,   pass_kernel<T, AX, Op, kMaxT, true, 6>};
     const K kern = variants[2 * ct + (early ? 1 : 0)];
     static std::once_flag attr_once;  // one attribute call per instantiation set (thread-safe)
     std::call_once(attr_once, [&] {
