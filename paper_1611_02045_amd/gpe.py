@@ -130,6 +130,10 @@ def make_problem(dim: int, n, L, beta: float, omega: float) -> Problem:
 
 
 def default_opts(**kw) -> PcgOpts:
+    """gpe_pcg_opts_t with the library's defaults, overridden by keyword: any field of PcgOpts, plus
+    the aliases tol / tol_res (tol_res_inf) and names for the enumerations: precond ("none",
+    "kinetic", "potential", "combined", "c1", "c2"), method ("pg", "pcg"), precision ("fp64",
+    "mixed"), beta_rule ("pr", "fr"), line_search ("heuristic", "armijo", "full", "wolfe")."""
     o = PcgOpts()
     lib().gpe_pcg_opts_default(ctypes.byref(o))
     alias = {"tol": "tol_res_inf", "tol_res": "tol_res_inf"}
@@ -264,7 +268,8 @@ class Plan:
 
     # -- solver ---------------------------------------------------------------------------------
     def pcg_solve(self, V, phi, stream=None, **opts):
-        """Solve in place (phi is overwritten by the final iterate); returns the report dict."""
+        """Solve in place (phi is overwritten by the final iterate); returns the report dict.  opts: see
+        default_opts."""
         o = default_opts(**opts)
         rep = PcgReport()
         st = lib().gpe_pcg_solve(self._h, self._field(V, "V", False), self._field(phi, "phi"), ctypes.byref(o),
