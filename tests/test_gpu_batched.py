@@ -167,3 +167,30 @@ def test_converged_instances_inside_a_part_leave_the_launches(torch_gpu, precisi
         assert rep["iters"] == reps[k]["iters"] and rep["iters"] > 40
         assert rep["E"] == reps[k]["E"]
         assert torch.equal(alone, phis[k])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_bench_workload_states_pass_the_oracle(torch_gpu, precision):
+    """The benchmark's own configuration: the eight seeded 512^2 starts (Omega = 0.9, beta = 1000),
+    one batched solve to 1e-8 with the default options (two parts on two streams, graph replay),
+    exactly as the bench times it.  Every final state is re-evaluated by the oracle: unit norm,
+    ||r||_inf <= 1e-8 (plus rounding of the reported value), the reported energy, and an energy in
+    the band of the workload's local minima."""
+    from gpe_inputs import workload_2d_set
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, starts = workload_2d_set(512)
+    Vd = torch.from_numpy(V).to("cuda")
+    phis = [torch.from_numpy(s).to("cuda") for s in starts]
+    print(f"bench workload {precision}", flush=True)
+    st, reps = gpe.pcg_solve_batched([prob] * len(phis), [Vd] * len(phis), phis, "f64", tol=1e-8,
+                                     precision=precision, max_iter=200000)
+    assert st == 0, [r["status"] for r in reps]
+    for rep, phi in zip(reps, phis):
+        got = phi.cpu().numpy()
+        assert abs(O.norm(prob, got) - 1.0) < 1e-12
+        r, _ = O.residual(prob, V, got)
+        assert float(np.max(np.abs(r))) <= 1.5e-8
+        E = O.energy(prob, V, got)
+        assert abs(E - rep["E"]) < 1e-11 * abs(E)
+        assert 6.3600 < E < 6.3610
