@@ -180,7 +180,7 @@ int gpe_pcg_solve(gpe_plan_t* plan, const void* V, void* phi_inout, const gpe_pc
 int gpe_pcg_history(gpe_plan_t* plan, double* hist, int cap);
 
 /* Independent solves of `count` problems (possibly different grids, beta, omega, L); instances
- * of equal grid share each kernel launch and converged instances are masked out.  The instances
+ * of equal grid share each kernel launch and converged instances leave the launches.  The instances
  * of a grid are split into two parts, and the parts of all grids are solved concurrently, each
  * on its own stream (the caller's for the first, default-priority streams the call creates for
  * the others) driven by its own host thread; the created streams first wait for the work already
