@@ -151,6 +151,23 @@ def test_apply_H_batched(torch_gpu, dtype):
         assert _relerr(out[b], O.hamiltonian(prob, V, phis[b])) < TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_apply_H_batch32_at_512(torch_gpu, dtype):
+    """The bench's apply configuration: 32 fields of 512^2 (Omega = 0.9, beta = 1000) in one batched
+    apply; sampled instances (first, middle, last) against the oracle."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob = Problem(2, (512, 512), (16.0, 16.0), 1000.0, 0.9)
+    V = harmonic_potential(prob)
+    base = random_field(prob, 21, envelope=0.02)
+    phis = np.stack([base * (1.0 + 0.01 * k) * np.exp(0.1j * k) for k in range(32)])
+    print(f"apply batch 32 at 512^2 {dtype}", flush=True)
+    plan = gpe.Plan.from_problem(prob, dtype)
+    out = plan.apply_H_batched(_to(torch, phis, dtype), _to(torch, V, dtype)).cpu().numpy()
+    for b in (0, 15, 31):
+        assert _relerr(out[b], O.hamiltonian(prob, V, phis[b])) < TOL[dtype]
+
+
 def test_energy_grad(torch_gpu):
     """grad_phi = 2 h^d H phi, grad_V = h^d |phi|^2, dE/dbeta, dE/domega against the oracle."""
     from paper_1611_02045_amd import gpe
