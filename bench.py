@@ -357,6 +357,15 @@ def main():
                                                                       precision=prec)
         for k, v in configs.items():
             log(f"[bench] config {k}: {v['s']:.4f} s, {v['iters']} iterations, E = {v['E']:.10f}, {v['status']}")
+        # the paper's fast-rotation series on its own grid: Omega = 1 ... 4.5 at eta = 1000, 640^2 points
+        # of [-20, 20]^2, Thomas-Fermi start, FP64 PCG to 1e-8
+        series = {}
+        for om in (1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 4.5):
+            pq, Vq, fq = workload_quartic_2d(640, om, 1000.0)
+            series[f"{om:g}"] = timed_solve(pq, Vq, fq, "f64", tol=1e-8, max_iter=200000)
+        configs["2d_640_quartic_omega_series_fp64"] = series
+        log("[bench] fast-rotation series on 640^2 (Omega: s, iterations): " +
+            ", ".join(f"{k}: {v['s']:.3f} s {v['iters']}" for k, v in series.items()))
 
     # the differentiation workload (2-D 256^2 on [-16, 16]^2, beta = 1000, Omega = 0.85, harmonic trap
     # with 9 Gaussian pins): loss = E(phi*) + h^2 sum (|phi*|^2 - rho_t)^2, rho_t from a solve at the
