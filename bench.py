@@ -158,6 +158,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the 64-instance sweep")
     ap.add_argument("--no-configs", action="store_true", help="skip the 1-D, 2-D 256^2 and 3-D single solves")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="also solve the paper's fast-rotation table (eta = 1000, 5000, 10000 x Omega = 1 ... 4.5 on "
+                         "640^2 points of [-20, 20]^2, its stopping rule |E_n+1 - E_n| <= 1e-14), about a minute")
     ap.add_argument("--no-step-rules", action="store_true",
                     help="skip the Armijo / full / Wolfe line search and Fletcher-Reeves solves")
     ap.add_argument("--tol-coarse", type=float, default=1e-5, help="residual tolerance of the coarse nested grids")
@@ -411,6 +414,26 @@ def main():
                 "grad": [float(t.grad.item()) for t in theta]}
         log(f"[bench] differentiation: forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s, grad {diff['grad']}")
 
+    # the paper's fast-rotation table on its grid with its stopping rule (opt-in: about a minute)
+    table = None
+    if args.paper_table:
+        from gpe_inputs import workload_quartic_2d
+        table = {}
+        for eta in (1000.0, 5000.0, 10000.0):
+            row = {}
+            for om in (1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 4.5):
+                pq, Vq, fq = workload_quartic_2d(640, om, eta)
+                pl = gpe.Plan.from_problem(pq, "f64")
+                Vd, ph = torch.from_numpy(Vq).to("cuda"), torch.from_numpy(fq.copy()).to("cuda")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = pl.pcg_solve(Vd, ph, tol=0.0, tol_energy=1e-14, max_iter=100000)
+                torch.cuda.synchronize()
+                row[f"{om:g}"] = {"s": time.perf_counter() - t0, "iters": r["iters"], "E": r["E"],
+                                  "res_inf": r["res_inf"], "status": r["status_name"]}
+            table[f"{eta:g}"] = row
+            log(f"[bench] paper table eta = {eta:g}: " + ", ".join(f"{k}: {v['s']:.2f} s" for k, v in row.items()))
+
     # H_phi applies/s (single field and a batch of 32 fields, FP64 and FP32)
     log("[bench] H applies")
     plan64 = gpe.Plan.from_problem(prob, "f64")
@@ -496,6 +519,7 @@ def main():
         "single_start": single,
         "step_rules": step_rules,
         "differentiation": diff,
+        "paper_table_640": table,
         "nested_grids": nested,
         "sweep_64": sweep,
         "other_configs": configs,
