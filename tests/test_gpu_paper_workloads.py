@@ -112,3 +112,23 @@ def test_fast_rotation_in_quartic_trap_512(torch_gpu):
     parts = O.energy_parts(prob, V, out)
     assert abs(parts.total - rep["E"]) < 1e-12 * abs(rep["E"])
     assert parts.rotation < -1.0  # the rotating state carries angular momentum
+
+
+@pytest.mark.parametrize("eta,omega", [(1000.0, 4.5), (10000.0, 1.0)])
+def test_fast_rotation_table_cells_with_the_energy_rule(torch_gpu, eta, omega):
+    """Two cells of the paper's fast-rotation table on its 640^2 grid, stopped by its rule
+    |E_{n+1} - E_n| <= 1e-14 (no residual test): the solve ends OK, and the oracle confirms the
+    reported energy, the unit norm and a small residual (the energy rule stops at ||r||_inf ~ 1e-5)."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob, V, start = workload_quartic_2d(640, omega, eta)
+    plan = gpe.Plan.from_problem(prob, "f64")
+    phi = _to(torch, start)
+    print(f"table cell eta={eta:g} Omega={omega:g}", flush=True)
+    rep = plan.pcg_solve(_to(torch, V), phi, tol=0.0, tol_energy=1e-14, max_iter=100000)
+    assert rep["status_name"] == "ok"
+    out = phi.cpu().numpy()
+    assert abs(O.norm(prob, out) - 1.0) < 1e-12
+    assert abs(O.energy(prob, V, out) - rep["E"]) < 1e-12 * abs(rep["E"])
+    r, _ = O.residual(prob, V, out)
+    assert np.max(np.abs(r)) < 1e-4
