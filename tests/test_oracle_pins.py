@@ -355,6 +355,178 @@ def test_preconditioner_rejects_non_positive_shift():
         O.apply_preconditioner(prob, "potential", V, phi, phi, alpha=1.0)
 
 
+def _real_matrix(prob, apply):
+    """Matrix of a real-linear map of C^N written on R^{2N} = (Re, Im) (dense, tiny grids)."""
+    N = prob.size
+    out = np.zeros((2 * N, 2 * N))
+    for k in range(2 * N):
+        e = np.zeros(2 * N)
+        e[k] = 1.0
+        f = apply((e[:N] + 1j * e[N:]).reshape(prob.shape)).ravel()
+        out[:, k] = np.concatenate([f.real, f.imag])
+    return out
+
+
+def _preconditioned_hessian_spectrum(prob, V, phi, kind):
+    """Eigenvalues of P A on {phi, i phi}^perp, A = (1/2) nabla^2 E(phi) - lambda, assembled
+    densely (numpy QR for the subspace, Cholesky of the restricted P, numpy eigvalsh)."""
+    lam = O.chemical_potential(prob, V, phi)
+    alpha = O.characteristic_energy(prob, V, phi)
+    A = _real_matrix(prob, lambda f: O.hessian_apply(prob, V, phi, f) - lam * f)
+    P = _real_matrix(prob, lambda f: O.apply_preconditioner(prob, kind, V, phi, f, alpha=alpha))
+    f = phi.ravel()
+    Y = np.stack([np.concatenate([f.real, f.imag]), np.concatenate([-f.imag, f.real])], axis=1)
+    Q = np.linalg.qr(np.concatenate([Y, np.eye(2 * prob.size)], axis=1))[0][:, 2:]
+    AQ = Q.T @ A @ Q
+    PQ = Q.T @ P @ Q
+    C = np.linalg.cholesky(0.5 * (PQ + PQ.T))
+    return np.linalg.eigvalsh(C.T @ (0.5 * (AQ + AQ.T)) @ C)
+
+
+def _condition_numbers(L, h, beta=10.0):
+    prob = Problem(1, (int(round(2 * L / h)),), (float(L),), beta, 0.0)
+    V = harmonic_potential(prob)
+    res = O.pcg(prob, V, gaussian(prob), tol_res=1e-11, max_iter=5000)
+    assert res.status == "converged"
+    out = {}
+    for kind in ("kinetic", "potential", "combined"):
+        w = _preconditioned_hessian_spectrum(prob, V, res.phi, kind)
+        assert w[0] > 0.0
+        out[kind] = w[-1] / w[0]
+    return out
+
+
+_WIDTHS = (6.0, 12.0, 24.0)    # at h = 1/4
+_STEPS = (0.5, 0.25, 0.125)    # at L = 8
+
+
+def _section_5_5_scalings():
+    byL = [_condition_numbers(L, 0.25) for L in _WIDTHS]
+    byh = [_condition_numbers(8.0, h) for h in _STEPS]
+    return byL, byh
+
+
+def _bounded(vals, spread=1.15):
+    return max(vals) / min(vals) < spread
+
+
+def test_condition_numbers_scale_as_section_5_5():
+    """Section 5.5's asymptotic condition numbers of the preconditioned Hessian (1-D harmonic trap,
+    ground state, dense spectra): kappa_Delta grows like L^p (p = 2) at fixed h and stays bounded
+    in h; kappa_V grows like h^-2 at fixed L and stays bounded in L; the combined preconditioner
+    is below both.  Doubling L twice (h fixed) multiplies kappa_Delta by about 16, halving h twice
+    multiplies kappa_V by about 16; a P_V without V (or with the wrong sign of it) grows with L."""
+    byL, byh = _section_5_5_scalings()
+    kd_L, kv_L = [k["kinetic"] for k in byL], [k["potential"] for k in byL]
+    kd_h, kv_h = [k["kinetic"] for k in byh], [k["potential"] for k in byh]
+    assert kd_L[2] / kd_L[0] > 8.0 and kd_L[1] / kd_L[0] > 3.0      # O(L^2)
+    assert _bounded(kd_h)                                           # independent of h
+    assert kv_h[2] / kv_h[0] > 8.0 and kv_h[1] / kv_h[0] > 2.5      # O(h^-2)
+    assert _bounded(kv_L)                                           # independent of L
+    for k in byL + byh:
+        assert k["combined"] < 0.5 * min(k["kinetic"], k["potential"])
+
+
+def test_condition_number_pin_rejects_a_potential_preconditioner_without_v(monkeypatch):
+    """The scaling pin above fails for a P_V that leaves V out of its diagonal (the mistake is
+    planted in the oracle here, on the CPU): kappa_V then grows with the box like kappa_Delta."""
+    monkeypatch.setattr(O, "potential_diagonal",
+                        lambda prob, V, phi, alpha: alpha + prob.beta * np.abs(phi) ** 2)
+    kv_L = [_condition_numbers(L, 0.25)["potential"] for L in _WIDTHS]
+    assert not _bounded(kv_L)
+
+
+@pytest.mark.parametrize("precond", ["combined", "kinetic"])
+def test_pcg_contracts_at_the_conjugate_gradient_rate(precond):
+    """beta = 0, Omega = 0 (1-D harmonic trap): near the ground state the problem is quadratic on
+    the tangent space with operator P (H - lambda_1), so the CG direction of Section 5.2 must
+    contract the residual at the conjugate-gradient rate (sqrt(kappa) - 1)/(sqrt(kappa) + 1),
+    and the projected gradient (beta_n = 0) at the steepest-descent rate (kappa - 1)/(kappa + 1)
+    (the square-root-of-the-condition-number dependence that Section 4 contrasts with
+    fixed-point schemes), with kappa from the dense spectrum.  A CG coefficient with a dropped
+    or misplaced term loses the square root."""
+    prob = Problem(1, (128,), (10.0,), 0.0, 0.0)
+    V = harmonic_potential(prob)
+    phi0 = random_field(prob, 5, envelope=0.05)
+    ground = O.pcg(prob, V, phi0, tol_res=1e-13, max_iter=3000)
+    w = _preconditioned_hessian_spectrum(prob, V, ground.phi, precond)
+    kappa = w[-1] / w[0]
+    cg_rate = (math.sqrt(kappa) - 1.0) / (math.sqrt(kappa) + 1.0)
+    sd_rate = (kappa - 1.0) / (kappa + 1.0)
+
+    def observed(method):
+        res = O.pcg(prob, V, phi0, method=method, precond=precond, tol_res=1e-13, max_iter=2000, record=True)
+        r = np.array([h["res"] for h in res.history])
+        i0, i1 = len(r) // 4, 3 * len(r) // 4
+        return (r[i1] / r[i0]) ** (1.0 / (i1 - i0))
+
+    pcg_rate, pg_rate = observed("pcg"), observed("pg")
+    assert 1.0 - pcg_rate > 0.6 * (1.0 - cg_rate)
+    assert 1.0 - pg_rate < 1.5 * (1.0 - sd_rate)
+    assert 1.0 - pg_rate < 0.6 * (1.0 - cg_rate)    # the gradient method fails the CG bound
+
+
+# ----------------------------------------------------------------------------------------------
+# Second-order condition (Section 2): the curvature check used on converged GPU states
+# ----------------------------------------------------------------------------------------------
+
+def test_second_order_check_closed_forms_at_beta0():
+    """beta = 0: on {phi_1, i phi_1}^perp the operator H - lambda_1 has smallest eigenvalue
+    lambda_2 - lambda_1, known in closed form for the harmonic oscillator: 1 in 1-D (levels
+    n + 1/2), 1/2 in 2-D at Omega = 1/2 (levels 2 n_r + |m| + 1 - Omega m: the m = +1 state is
+    next).  The unpreconditioned check must return it as its smallest Ritz value."""
+    for prob, gap in ((Problem(1, (64,), (8.0,), 0.0, 0.0), 1.0),
+                      (Problem(2, (48, 48), (8.0, 8.0), 0.0, 0.5), 0.5)):
+        V = harmonic_potential(prob)
+        chk = O.second_order_check(prob, V, gaussian(prob), random_field(prob, 9, envelope=0.05),
+                                   tol=1e-11, precond="none")
+        assert not chk.negative
+        assert abs(chk.min_ritz - gap) < 1e-8
+        pre = O.second_order_check(prob, V, gaussian(prob), random_field(prob, 9, envelope=0.05), tol=1e-9)
+        assert not pre.negative and pre.min_ritz > 0.0
+
+
+def test_second_order_check_flags_excited_states():
+    """Stationary states that are not minima: the first excited oscillator state x e^{-x^2/2}
+    (1-D) and the vortex (x + i y) e^{-r^2/2} at Omega = 1/2 (2-D), beta = 0.  Both are exact
+    eigenstates, so residual ~ 0, yet the ground state direction lowers the energy.  The check
+    must return a direction of negative curvature, and the plain energy must fall along it."""
+    p1 = Problem(1, (64,), (8.0,), 0.0, 0.0)
+    (x,) = mesh(p1)
+    p2 = Problem(2, (48, 48), (8.0, 8.0), 0.0, 0.5)
+    X, Y = mesh(p2)
+    for prob, phi in ((p1, x * np.exp(-0.5 * x ** 2) + 0j), (p2, (X + 1j * Y) * np.exp(-0.5 * (X ** 2 + Y ** 2)))):
+        phi = phi / O.norm(prob, phi)
+        V = harmonic_potential(prob)
+        r, _ = O.residual(prob, V, phi)
+        assert np.max(np.abs(r)) < 1e-10
+        for kind in ("none", "combined"):
+            chk = O.second_order_check(prob, V, phi, random_field(prob, 10, envelope=0.05), precond=kind)
+            assert chk.negative and chk.rayleigh < 0.0
+            # at a stationary point E(phi + t h normalised) - E(phi) = t^2 (curvature) + O(t^3)
+            h = O.project_gauge(prob, phi, chk.direction)
+            h = h / O.norm(prob, h)
+            t = 1e-3
+            moved = (phi + t * h) / O.norm(prob, phi + t * h)
+            drop = (O.energy(prob, V, moved) - O.energy(prob, V, phi)) / t ** 2
+            assert drop < 0.0 and abs(drop - chk.rayleigh) < 0.05 * abs(chk.rayleigh)
+
+
+def test_second_order_check_matches_the_dense_spectrum():
+    """A nonlinear rotating state on a tiny grid: the check's smallest Ritz value of P A equals
+    the smallest eigenvalue of the densely assembled preconditioned Hessian (numpy eigvalsh)."""
+    prob = Problem(2, (16, 16), (5.0, 5.0), 30.0, 0.5)
+    V = harmonic_potential(prob)
+    res = O.pcg(prob, V, paper_initial(prob, "d", 0.5), tol_res=1e-12, max_iter=5000)
+    assert res.status == "converged"
+    w = _preconditioned_hessian_spectrum(prob, V, res.phi, "combined")
+    assert w[0] > 0.0
+    chk = O.second_order_check(prob, V, res.phi, random_field(prob, 12), tol=1e-12)
+    assert not chk.negative
+    assert abs(chk.min_ritz - w[0]) < 1e-6 * w[-1]
+    assert abs(chk.max_ritz - w[-1]) < 1e-6 * w[-1]
+
+
 # ----------------------------------------------------------------------------------------------
 # Gradient-flow schemes (Section 4) and the PG/FE equivalence (Section 5.1)
 # ----------------------------------------------------------------------------------------------
