@@ -747,7 +747,7 @@ class CurvatureCheck:
 
 
 def second_order_check(prob, V, phi, rhs, *, tol: float = 1e-6, max_iter: int = 3000,
-                       precond: str = "combined") -> CurvatureCheck:
+                       precond: str = "combined", shift: float = 0.0, progress=None) -> CurvatureCheck:
     """Second-order condition of Section 2 at a stationary state phi: for every tangent h,
     (1/2) nabla^2 E(phi)[h, h] - lambda ||h||^2 >= 0, strictly on {phi, i phi}^perp for a strict
     local minimum (the global phase i phi is a null direction of every state).
@@ -758,12 +758,19 @@ def second_order_check(prob, V, phi, rhs, *, tol: float = 1e-6, max_iter: int = 
     that reaches ``tol`` with every curvature positive has resolved every eigen-component of the
     right-hand side above that level.  The Lanczos matrix T of the run (diagonal 1/a_k +
     b_{k-1}/a_{k-1}, off-diagonal sqrt(b_k)/a_k from the CG step lengths a_k and ratios b_k)
-    gives the Ritz values of P A.  precond="none" gives those of A itself."""
+    gives the Ritz values of P A.  precond="none" gives those of A itself.
+
+    shift > 0 checks A + shift instead, i.e. the weaker condition that no tangent curvature lies
+    below -shift: directions of curvature in [-shift, 0] count as flat.  (Degenerate families of
+    minima, such as the rotations of a vortex lattice in an isotropic trap, leave curvatures at
+    rounding level of either sign.)  The reported Ritz values are those of P (A + shift);
+    ``rayleigh`` is always that of A.  progress, if given, is called as progress(step, relative
+    residual) every 100 steps."""
     lam = chemical_potential(prob, V, phi)
     alpha = characteristic_energy(prob, V, phi)
 
     def A(f):
-        return project_gauge(prob, phi, hessian_apply(prob, V, phi, f) - lam * f)
+        return project_gauge(prob, phi, hessian_apply(prob, V, phi, f) - (lam - shift) * f)
 
     def P(f):
         f = project_gauge(prob, phi, f)
@@ -783,13 +790,15 @@ def second_order_check(prob, V, phi, rhs, *, tol: float = 1e-6, max_iter: int = 
         q = A(p)
         pq = inner(prob, p, q).real
         if pq <= 0.0:
-            return CurvatureCheck(True, float("nan"), float("nan"), pq / inner(prob, p, p).real, k, rel, p)
+            return CurvatureCheck(True, float("nan"), float("nan"), pq / inner(prob, p, p).real - shift, k, rel, p)
         a = rz / pq
         steps.append(a)
         r = r - a * q
         rel = math.sqrt(inner(prob, r, r).real) / b2
         if rel <= tol:
             break
+        if progress is not None and (k + 1) % 100 == 0:
+            progress(k + 1, rel)
         z = P(r)
         rz_new = inner(prob, r, z).real
         ratios.append(rz_new / rz)

@@ -236,8 +236,11 @@ struct PrivateStream {
     }
 };
 
-// An instantiated graph captured from work queued on one stream, under capture_mutex (other host
-// threads may launch meanwhile, but not allocate or touch the legacy stream).  Captures only kernel
+// An instantiated graph captured from work queued on one stream.  Every graph call of the library
+// (capture and instantiation, launch, destruction) holds capture_mutex: instantiating a graph and
+// destroying its executable allocate and free the device memory that holds the graph's kernel
+// arguments, which the mutex keeps out of other host threads' capture windows like every other
+// allocation and free, and no two host threads run graph calls at once.  Captures only kernel
 // launches: no memory-set or copy nodes.
 struct GraphExec {
     hipGraphExec_t exec = nullptr;
@@ -258,13 +261,18 @@ struct GraphExec {
         if (e != hipSuccess) exec = nullptr;
         return e;
     }
+    hipError_t launch(hipStream_t s) {
+        std::lock_guard<std::mutex> lock(capture_mutex());
+        return hipGraphLaunch(exec, s);
+    }
     void reset() {
-        if (exec) (void)hipGraphExecDestroy(exec);
+        if (exec) {
+            std::lock_guard<std::mutex> lock(capture_mutex());
+            (void)hipGraphExecDestroy(exec);
+        }
         exec = nullptr;
     }
-    ~GraphExec() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-    }
+    ~GraphExec() { reset(); }
 };
 
 template <typename T>
@@ -346,7 +354,7 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
                 return e;
         }
         if (graph.exec) {
-            if ((e = hipGraphLaunch(graph.exec, s)) != hipSuccess) return e;
+            if ((e = graph.launch(s)) != hipSuccess) return e;
         } else {
             for (int k = 0; k < pa.check_every; ++k) {
                 if ((e = enqueue_iteration<T>(c, s)) != hipSuccess) return e;
@@ -401,7 +409,6 @@ hipError_t run_phase(PhaseArgs& pa, IterFields<T> f, std::vector<Scal>& host_S, 
                     gb.L[a] = host_S[b].L[a];
                     gb.h[a] = host_S[b].h[a];
                     gb.dk[a] = host_S[b].dk[a];
-            gb.dk[a] = host_S[b].dk[a];
                 }
                 gb.cell = host_S[b].cell;
                 if ((e = refresh_instance<T>(gb, *pa.tw, c.f, (int64_t)b * N, S_dir + b, host_S[b].beta,

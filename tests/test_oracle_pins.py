@@ -482,6 +482,9 @@ def test_second_order_check_closed_forms_at_beta0():
                                    tol=1e-11, precond="none")
         assert not chk.negative
         assert abs(chk.min_ritz - gap) < 1e-8
+        shifted = O.second_order_check(prob, V, gaussian(prob), random_field(prob, 9, envelope=0.05),
+                                       tol=1e-11, precond="none", shift=0.125)
+        assert abs(shifted.min_ritz - (gap + 0.125)) < 1e-8
         pre = O.second_order_check(prob, V, gaussian(prob), random_field(prob, 9, envelope=0.05), tol=1e-9)
         assert not pre.negative and pre.min_ritz > 0.0
 
@@ -500,9 +503,10 @@ def test_second_order_check_flags_excited_states():
         V = harmonic_potential(prob)
         r, _ = O.residual(prob, V, phi)
         assert np.max(np.abs(r)) < 1e-10
-        for kind in ("none", "combined"):
-            chk = O.second_order_check(prob, V, phi, random_field(prob, 10, envelope=0.05), precond=kind)
-            assert chk.negative and chk.rayleigh < 0.0
+        for kind, shift in (("none", 0.0), ("combined", 0.0), ("combined", 1e-9)):
+            chk = O.second_order_check(prob, V, phi, random_field(prob, 10, envelope=0.05), precond=kind,
+                                       shift=shift)
+            assert chk.negative and chk.rayleigh < -shift
             # at a stationary point E(phi + t h normalised) - E(phi) = t^2 (curvature) + O(t^3)
             h = O.project_gauge(prob, phi, chk.direction)
             h = h / O.norm(prob, h)
