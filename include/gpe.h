@@ -31,6 +31,7 @@
 #ifndef GPE_H
 #define GPE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -90,6 +91,20 @@ int gpe_apply_H(gpe_plan_t* plan, const void* phi, const void* V, void* Hphi, vo
  * the plan's problem and the same potential V.  Asynchronous. */
 int gpe_apply_H_batched(gpe_plan_t* plan, int count, const void* phi, const void* V, void* Hphi,
                         void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): gpe_apply_H_batched without any allocation.  The
+ * intermediate of its two (2-D) or three (3-D) directional passes lives in a static device array
+ * of GPE_NOALLOC_SCRATCH_BYTES per device, held until the process ends, instead of the plan's
+ * growable workspace; the plan must have been created on the current device.  Same arguments,
+ * layout and results as gpe_apply_H_batched (the same kernels run).  Requires
+ * count * N * (16 for FP64, 8 for FP32) <= GPE_NOALLOC_SCRATCH_BYTES, else GPE_EINVAL and nothing
+ * is launched.  Every call on one device shares that device's array: calls that overlap on one
+ * device (concurrent streams or host threads) race and must be ordered by the caller.
+ * Asynchronous. */
+#define GPE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int gpe_apply_H_batched_noalloc(gpe_plan_t* plan, int count, const void* phi, const void* V, void* Hphi,
+                                void* stream);
 
 /* Pr = P r for the preconditioner `kind` of Section 5.5 at the point phi, with shift alpha.
  * alpha = NaN selects the adaptive shift lambda~(phi) = <phi,T phi> + <phi,V phi> +

@@ -62,6 +62,7 @@ SIGNATURES = {
     "gpe_energy": (_I, [_VP, _VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), _VP]),
     "gpe_apply_H": (_I, [_VP, _VP, _VP, _VP, _VP]),
     "gpe_apply_H_batched": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
+    "gpe_apply_H_batched_noalloc": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
     "gpe_precond": (_I, [_VP, _I, _VP, _VP, _D, _VP, _VP, _VP]),
     "gpe_pcg_opts_default": (None, [ctypes.POINTER(PcgOpts)]),
     "gpe_pcg_solve": (_I, [_VP, _VP, _VP, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
@@ -226,6 +227,15 @@ class Plan:
         _check(lib().gpe_apply_H_batched(self._h, count, self._field(phi, "phi", batch=count),
                                          self._field(V, "V", False), self._field(out, "out", batch=count),
                                          _stream(stream)))
+        return out
+
+    def apply_H_batched_noalloc(self, phi, V, out, stream=None):
+        """gpe_apply_H_batched_noalloc: the batched apply with its intermediate in the library's
+        static device scratch (no allocation; `out` must be given)."""
+        count = int(phi.shape[0])
+        _check(lib().gpe_apply_H_batched_noalloc(self._h, count, self._field(phi, "phi", batch=count),
+                                                 self._field(V, "V", False), self._field(out, "out", batch=count),
+                                                 _stream(stream)))
         return out
 
     def autotune(self, count: int = 1, stream=None):
