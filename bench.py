@@ -119,30 +119,64 @@ def applies_per_s_graph(torch, plan, phi, V, reps=1000):
     return reps / (e0.elapsed_time(e1) / 1e3)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(prob, V, phi0, iters, gpu_fp64_iters_total):
-    """The FP64 oracle, as it stands, on the same workload for a bounded number of iterations."""
+    """The FP64 oracle, as it stands, on the GPU machine's host: PCG iterations/s and H_phi applies/s on
+    the 512^2 workload (bounded samples), the 1-D 256-point configuration solved to 1e-10 and the
+    2-D 256^2 and 3-D 128^3 configurations sampled, all on one thread (numpy's transforms are
+    single-threaded; BLAS is held to one thread so that the figure does not depend on the box's
+    core count)."""
+    from gpe_inputs import workload_1d, workload_2d, workload_3d
     from oracle import gpe_oracle as O
     try:
         from threadpoolctl import threadpool_limits
         ctx = threadpool_limits(1)
     except Exception:  # pragma: no cover
         ctx = None
-    t0 = time.perf_counter()
-    res = O.pcg(prob, V, phi0, tol_res=1e-8, max_iter=iters)
-    sec = time.perf_counter() - t0
-    if ctx is not None and hasattr(ctx, "unregister"):
-        ctx.unregister()
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        r = fn()
+        return r, time.perf_counter() - t0
+
+    res, sec = timed(lambda: O.pcg(prob, V, phi0, tol_res=1e-8, max_iter=iters))
     done = max(1, res.iters)
     it_s = done / sec
+    phi = phi0 / O.norm(prob, phi0)
+    _, ha = timed(lambda: [O.hamiltonian(prob, V, phi) for _ in range(10)])
+    p1, V1, f1 = workload_1d()
+    r1, s1 = timed(lambda: O.pcg(p1, V1, f1, tol_res=1e-10, max_iter=5000))
+    p2, V2, f2 = workload_2d(256)
+    r2, s2 = timed(lambda: O.pcg(p2, V2, f2, tol_res=1e-8, max_iter=40))
+    p3, V3, f3 = workload_3d(128)
+    r3, s3 = timed(lambda: O.pcg(p3, V3, f3, tol_res=1e-8, max_iter=3))
+    if ctx is not None and hasattr(ctx, "unregister"):
+        ctx.unregister()
     return {
         "value": gpu_fp64_iters_total / it_s,
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"numpy FP64 oracle, PCG_C on the first 512^2 start, {done} iterations ({sec:.1f} s, "
-                   f"{it_s:.2f} it/s, 1 thread), extrapolated to one step: the {gpu_fp64_iters_total} iterations "
+        "sample": (f"numpy FP64 oracle on {cpu_model()} (1 thread), PCG_C on the first 512^2 start, {done} iterations "
+                   f"({sec:.1f} s, {it_s:.2f} it/s), extrapolated to one step: the {gpu_fp64_iters_total} iterations "
                    f"the eight starts take to 1e-8 in FP64 on the GPU, solved one after another"),
+        "cpu_model": cpu_model(),
         "iters_per_s": it_s,
+        "h_applies_per_s_512": 10.0 / ha,
+        "c1_1d_256_to_1e-10": {"s": s1, "iters": r1.iters, "E": r1.E, "status": r1.status},
+        "c2_2d_256_iters_per_s": r2.iters / s2,
+        "c3_3d_128_iters_per_s": max(1, r3.iters) / s3,
     }
 
 
@@ -191,18 +225,44 @@ def main():
     fp64 = dict(tol=tol, precision="fp64", max_iter=200000)
     probs, Vs = [prob] * S, [V] * S
 
-    def profile(precision):
-        return gpe.pcg_profile_batched(probs, Vs, starts0, "f64", iters=args.profile_iters, precision=precision)
+    def profile(precision, count=S):
+        # `count` instances: the eight starts, repeated
+        ss = [starts0[k % S] for k in range(count)]
+        return gpe.pcg_profile_batched([prob] * count, [V] * count, ss, "f64", iters=args.profile_iters,
+                                       precision=precision)
+
+    def above_mall():
+        """Configurations whose working set exceeds the 256 MB Infinity Cache (MALL), so that their
+        HBM figures are DRAM figures: the step's iteration with 24 FP32 instances (8 FP32 fields + V
+        per instance: 24 x 17 MiB = 408 MiB), the FP64 iteration of the 8 starts (8 x 34 MiB =
+        272 MiB), and H applies over 64 FP32 fields (phi, H phi and the intermediate: 384 MiB) and 32
+        FP64 fields (384 MiB), timed per pass with HIP events on the launch stream."""
+        out = {"iteration_fp32_x24": kernel_rows(profile("mixed", 3 * S))}
+        pl32 = gpe.Plan.from_problem(prob, "f32")
+        pl64 = gpe.Plan.from_problem(prob, "f64")
+        for tag, pl, dt, n in (("apply_fp32_x64", pl32, torch.complex64, 64), ("apply_fp64_x32", pl64, torch.complex128, 32)):
+            bphi = starts0[0].to(dt).unsqueeze(0).repeat(n, 1, 1).contiguous()
+            Vd = V.float() if dt == torch.complex64 else V
+            rate, sec = applies_per_s(torch, pl, bphi, Vd, 10, batched=True)
+            cb = 8 if dt == torch.complex64 else 16
+            out[tag] = {"applies_per_s": rate, "s_per_launch_pair": sec,
+                        "GB_s_11sN": 11 * (cb // 2) * 512 * 512 * n / sec / 1e9}
+            del bphi
+        return out
 
     if args.profile_only:
+        for prec in ("mixed", "fp64"):  # first launches load the kernels: keep them out of the averages
+            gpe.pcg_profile_batched(probs, Vs, starts0, "f64", iters=2, precision=prec)
         prof32, prof64 = profile("mixed"), profile("fp64")
+        big = above_mall()
         # a plain copy of known size, to scale the HBM byte counters
         a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"profile_only": True, "copy_bytes": a.numel(),
-                          "kernels": {"fp32": kernel_rows(prof32), "fp64": kernel_rows(prof64)}}), flush=True)
+                          "kernels": {"fp32": kernel_rows(prof32), "fp64": kernel_rows(prof64)},
+                          "above_mall": big}), flush=True)
         return
 
     def step(opts):
@@ -483,7 +543,18 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
                 "kernel": kname, "bytes_per_launch": by, "avg_ms": ms,
-                "timing": f"HIP start/stop events recorded by each launch (kernel execution only), {S} instances"}
+                "timing": f"HIP start/stop events recorded by each launch (kernel execution only), {S} instances",
+                "cache": "the step's working set (8 FP32 instances, ~136 MiB) fits in the 256 MB MALL: "
+                         "see roofline_above_mall for the same kernel with a DRAM-sized working set"}
+    log("[bench] above-MALL profile")
+    big = above_mall()
+    row = next(r for r in big["iteration_fp32_x24"] if r["name"] == name)
+    roofline_big = {"bound": "hbm", "achieved": row["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": row["GB_s"] / HBM_PEAK_GBS, "traffic": measured_traffic(f"{name} (fp32 x24)"),
+                    "kernel": f"{name} (fp32)", "instances": 3 * S, "bytes_per_launch": row["bytes"],
+                    "avg_ms": row["avg_ms"], "working_set_MiB": 3 * S * (8 * 8 + 4) * 512 * 512 / 2 ** 20,
+                    "iteration": big["iteration_fp32_x24"], "fp64_iteration_x8": kernel_rows(prof64),
+                    "applies": {k: v for k, v in big.items() if k.startswith("apply")}}
 
     it_fp64_single = single["fp64"]["iters"] if single else [r["iters"] for r in reps_fp64]
     cpu = None
@@ -532,6 +603,7 @@ def main():
                   "E_fp64": [r["E"] for r in reps_fp64], "res_fp64": max(r["res_inf"] for r in reps_fp64)},
         "kernels": {"fp32": kernel_rows(prof32), "fp64": kernel_rows(prof64)},
         "roofline": roofline,
+        "roofline_above_mall": roofline_big,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -22,7 +22,9 @@ __device__ __forceinline__ double rot_coef(const Geo& g, const LineCtx& lc, doub
 
 // ---------------------------------------------------------------------------------------------
 // Directional part of L (and H): out = acc + F_a^{-1}[sigma_a F_a f], sigma_a = xi^2/2 + rot*xi,
-// and on the last axis also + (V + beta|f|^2) f (beta term only for the nonlinear H).
+// and on the pass with `pointwise` set also + (V + beta|f|^2) f (beta term only for the
+// nonlinear H).  The pointwise part goes with the x pass, where V is read contiguously; the
+// strided passes then read only f and the running sum.
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX>
 struct OpApply {
@@ -32,14 +34,19 @@ struct OpApply {
     const C2<T>* f;
     const C2<T>* acc;  // nullable
     C2<T>* out;
-    const T* V;        // used on the last axis
+    const T* V;        // used by the pass with `pointwise` set
     double beta, omega;
-    int last, nonlinear;
+    int pointwise, nonlinear;
     double kin = 1.0;  // weight of the kinetic symbol (0: rotation part only)
-    struct State { C2<T> f0[8]; };
+    // only the x pass carries the pointwise part: the strided passes keep no copy of f
+    static constexpr bool PW = AX == 0;
+    struct State { C2<T> f0[PW ? 8 : 1]; };
     __device__ void load(const Geo&, const LineCtx& lc, State& st, C2<T> (&v)[8], double (&acc)[K > 0 ? K : 1]) const {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) st.f0[s] = v[s] = f[lc.at(s)];
+        for (int s = 0; s < 8; ++s) {
+            v[s] = f[lc.at(s)];
+            if constexpr (PW) st.f0[s] = v[s];
+        }
     }
     template <int LG>
     __device__ void spectral(const Geo& g, const LineCtx& lc, State&, C2<T> (&v)[8], double (&)[1], C2<T>*,
@@ -58,10 +65,12 @@ struct OpApply {
             const int64_t i = lc.at(s);
             C2<T> o = v[s];
             if (acc) o = add(o, acc[i]);
-            if (last && V) {
-                T w = V[i - lc.off_b];
-                if (nonlinear) w += (T)beta * abs2(st.f0[s]);
-                o = add(o, scl(st.f0[s], w));
+            if constexpr (PW) {
+                if (pointwise && V) {
+                    T w = V[i - lc.off_b];
+                    if (nonlinear) w += (T)beta * abs2(st.f0[s]);
+                    o = add(o, scl(st.f0[s], w));
+                }
             }
             out[i] = o;
         }
@@ -79,16 +88,16 @@ static hipError_t apply_t(const Geo& g, int B, const Twiddles& tw, const void* f
         OpApply<T, 0> op{F, nullptr, (C2<T>*)out, (const T*)V, beta, omega, 1, nl};
         return launch_pass<T, 0>(g, B, tw.get(0, f64), op, none, s);
     }
-    // x-pass into tmp, then y (and z) passes accumulate; the last adds the pointwise part.
-    OpApply<T, 0> ox{F, nullptr, (C2<T>*)tmp, (const T*)V, beta, omega, 0, nl};
+    // x-pass (with the pointwise part) into tmp, then the y (and z) passes accumulate.
+    OpApply<T, 0> ox{F, nullptr, (C2<T>*)tmp, (const T*)V, beta, omega, 1, nl};
     if ((e = launch_pass<T, 0>(g, B, tw.get(0, f64), ox, none, s)) != hipSuccess) return e;
     if (g.dim == 2) {
-        OpApply<T, 1> oy{F, (const C2<T>*)tmp, (C2<T>*)out, (const T*)V, beta, omega, 1, nl};
+        OpApply<T, 1> oy{F, (const C2<T>*)tmp, (C2<T>*)out, nullptr, beta, omega, 0, nl};
         return launch_pass<T, 1>(g, B, tw.get(1, f64), oy, none, s);
     }
-    OpApply<T, 1> oy{F, (const C2<T>*)tmp, (C2<T>*)tmp, (const T*)V, beta, omega, 0, nl};
+    OpApply<T, 1> oy{F, (const C2<T>*)tmp, (C2<T>*)tmp, nullptr, beta, omega, 0, nl};
     if ((e = launch_pass<T, 1>(g, B, tw.get(1, f64), oy, none, s)) != hipSuccess) return e;
-    OpApply<T, 2> oz{F, (const C2<T>*)tmp, (C2<T>*)out, (const T*)V, beta, omega, 1, nl};
+    OpApply<T, 2> oz{F, (const C2<T>*)tmp, (C2<T>*)out, nullptr, beta, omega, 0, nl};
     return launch_pass<T, 2>(g, B, tw.get(2, f64), oz, none, s);
 }
 

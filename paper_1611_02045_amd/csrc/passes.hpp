@@ -202,6 +202,18 @@ struct WideRt<Op, std::void_t<decltype(Op::WIDE_RT)>> {
 template <class Op, int LG>
 constexpr bool kWideAt = LG == 0 || ct_f5(LG) ? WideRt<Op>::value : Op::WIDE;
 
+// Whether a late launch of an Op fetches its transform input (Op::prefetch) before begin(), with
+// the state intake: Op::PREFETCH_EARLY when the Op defines it (Ops whose prefetch is light enough
+// to hold in registers through begin()).
+template <class Op, class = void>
+struct PrefetchEarly {
+    static constexpr bool value = false;
+};
+template <class Op>
+struct PrefetchEarly<Op, std::void_t<decltype(Op::PREFETCH_EARLY)>> {
+    static constexpr bool value = Op::PREFETCH_EARLY;
+};
+
 // Twiddles per thread fetched into registers ahead of the scalar logic (more go straight to LDS).
 constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 
@@ -214,7 +226,7 @@ constexpr int kTwiddleRegs = 4;  // tw0..tw3 in pass_kernel
 //   __device__ void prefetch(const Geo&, const LineCtx&, State&) const;       // if PREFETCH: load()'s inputs
 //   __device__ void prefetch_tail(const Geo&, const LineCtx&, State&) const;  // if PREFETCH: store()'s inputs
 //   struct Intake;                                                                         // if SCALARS
-//   __device__ void intake(int b, Intake&) const;                                          // if SCALARS
+//   __device__ void intake(int b, int blk_in_inst, Intake&) const;                         // if SCALARS
 //   __device__ void begin(const Geo&, int b, int blk_in_inst, double* red, Scal* s, Intake&) const;  // if SCALARS
 //   __device__ void load(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K]) const;
 //   __device__ void spectral(const Geo&, const LineCtx&, State&, C2<T>(&)[8], double(&)[K],
@@ -252,7 +264,7 @@ void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op, Partials pr
     // bound by bandwidth) they are fetched when needed, which keeps the register footprint and
     // hence the occupancy that hides the latency.
     typename IntakeOf<Op>::type in;
-    if constexpr (Op::SCALARS) op.intake(lc.b, in);
+    if constexpr (Op::SCALARS) op.intake(lc.b, blk_in_inst, in);
     // (four named registers rather than an array, which the compiler may demote to scratch)
     auto tw_at = [&](int j) { return min((int)(threadIdx.x + j * blockDim.x), lc.M - 1); };
     C2<T> tw0, tw1, tw2, tw3;
@@ -270,6 +282,13 @@ void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op, Partials pr
         op.prefetch(g, lc, st);
         op.prefetch_tail(g, lc, st);
     }
+    // Late launches stage the twiddle table (and fetch a light transform input) before begin(), so
+    // that these loads share one memory round trip with the state intake.
+    constexpr bool kEarlyInput = !EARLY && Op::PREFETCH && PrefetchEarly<Op>::value;
+    if constexpr (!EARLY) {
+        for (int i = threadIdx.x; i < lc.M; i += blockDim.x) tw[i] = twg[i];
+        if constexpr (kEarlyInput) op.prefetch(g, lc, st);
+    }
     if constexpr (Op::SCALARS) {
         __shared__ Scal s_local;
         op.begin(g, lc.b, blk_in_inst, red, &s_local, in);  // all threads; ends with a barrier
@@ -286,8 +305,7 @@ void pass_kernel(Geo g, int C, const C2<T>* __restrict__ twg, Op op, Partials pr
         tw_put(2, tw2);
         tw_put(3, tw3);
         for (int i = threadIdx.x + kTwiddleRegs * blockDim.x; i < lc.M; i += blockDim.x) tw[i] = twg[i];
-    } else if constexpr (!EARLY) {
-        for (int i = threadIdx.x; i < lc.M; i += blockDim.x) tw[i] = twg[i];
+    } else if constexpr (!EARLY && !kEarlyInput) {
         if constexpr (Op::PREFETCH) op.prefetch(g, lc, st);
     }
     if constexpr (!kTwGlobal) __syncthreads();  // the LDS twiddle table is complete

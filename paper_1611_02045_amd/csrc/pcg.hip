@@ -628,7 +628,7 @@ struct OpResid {
     Partials pb;      // the direction passes' rows (consumer view)
     int pre, post;
     using Intake = IntakeStep;
-    __device__ void intake(int b, Intake& it) const { intake_step(Sin, pb, b, it); }
+    __device__ void intake(int b, int, Intake& it) const { intake_step(Sin, pb, b, it); }
     struct State {
         C2<T> ph[8], lph[8], pp[8], lp[8];
         T V[8];
@@ -705,11 +705,16 @@ struct OpResid {
 // ---------------------------------------------------------------------------------------------
 // Phase A, middle passes (y, z): forward and/or inverse transform with the kinetic multiplier
 // 1/(lambda~ + |k|^2/2) (with the 1/N of the inverse transforms) on the pass that does both.
-// The first middle pass (ABS) runs the convergence test on the first pass's sums.
+// The first middle pass (ABS) runs the convergence test on the first pass's sums, in the block
+// that publishes the instance's state (blk 0) only: the multiplier needs lambda~ alone, which the
+// step already put in S_step, so the other blocks start their transforms without waiting for the
+// reduction.  They also transform the lines of an instance that the test finds converged (their
+// output is never read).
 // ---------------------------------------------------------------------------------------------
 template <typename T, int AX, bool F, bool I, bool ABS>
 struct OpPMid {
     static constexpr bool FWD = F, INV = I, SCALARS = true, PREFETCH = true, WIDE = false;
+    static constexpr bool PREFETCH_EARLY = true;  // w only: eight points per thread
     static constexpr int K = 0;
     static constexpr unsigned MAXMASK = 0;
     C2<T>* w;
@@ -717,9 +722,10 @@ struct OpPMid {
     Scal* Sout;       // ABS: S_res
     Partials pa1;
     using Intake = std::conditional_t<ABS, IntakeA, IntakeState>;
-    __device__ void intake(int b, Intake& it) const {
+    __device__ void intake(int b, int blk, Intake& it) const {
         it.st.issue(Sin, b);
-        if constexpr (ABS) it.rows.issue(pa1, b, A_MAXMASK);
+        if constexpr (ABS)
+            if (blk == 0) it.rows.issue(pa1, b, A_MAXMASK);
     }
     struct State {
         C2<T> w[8];
@@ -731,14 +737,16 @@ struct OpPMid {
     __device__ void prefetch_tail(const Geo&, const LineCtx&, State&) const {}
     __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s, Intake& it) const {
         if constexpr (ABS) {
-            __shared__ double tot[A_K];
-            absorb_finish(Sin, b, blk, s, it, pa1, A_MAXMASK, red, tot, [](Scal& S, const double* t) {
-                if (!S.done) fin_residual(S, t);
-            });
-            state_publish(Sout, b, blk, s);
-        } else {
-            state_copy(Sin, b, s, it.st);
+            if (blk == 0) {
+                __shared__ double tot[A_K];
+                absorb_finish(Sin, b, blk, s, it, pa1, A_MAXMASK, red, tot, [](Scal& S, const double* t) {
+                    if (!S.done) fin_residual(S, t);
+                });
+                state_publish(Sout, b, blk, s);
+                return;
+            }
         }
+        state_copy(Sin, b, s, it.st);
     }
     __device__ void load(const Geo&, const LineCtx&, State& st, C2<T> (&v)[8], double (&)[1]) const {
 #pragma unroll
@@ -804,7 +812,7 @@ struct OpPLast {
         }
     }
     using Intake = IntakeState;
-    __device__ void intake(int b, Intake& it) const { it.st.issue(Sin, b); }
+    __device__ void intake(int b, int, Intake& it) const { it.st.issue(Sin, b); }
     __device__ void begin(const Geo&, int b, int, double*, Scal* s, Intake& it) const { state_copy(Sin, b, s, it.st); }
     __device__ void load(const Geo&, const LineCtx&, State& st, C2<T> (&v)[8], double (&)[K]) const {
 #pragma unroll
@@ -829,7 +837,7 @@ struct OpPLast {
 
 // ---------------------------------------------------------------------------------------------
 // Phase B: p = -P r + beta_cg p_{n-1} - rho phi (written over p_{n-1}), phat = p/||p||, and
-// L phat = sum_a F_a^{-1}[sigma_a F_a phat] + V phat.  When omega != 0 the passes along x and y
+// L phat = sum_a F_a^{-1}[sigma_a F_a phat] + V phat (V phat with the x part).  When omega != 0 the passes along x and y
 // also transform phi (forward only) to accumulate <phi, R phi>, Re<phi, R phat>, <phat, R phat>
 // (Parseval per line), which keeps lambda~ exact without a separate rotation field.  The first
 // pass runs the CG direction logic (and, on the one-pass paths, the convergence test).
@@ -846,7 +854,7 @@ struct OpLp {
     Partials pres;     // FIRST: set (to pdir's region) when the convergence test runs here (one-pass paths)
     Partials pdir;     // FIRST: sums for the CG direction
     using Intake = std::conditional_t<FIRST, IntakeA, IntakeState>;
-    __device__ void intake(int b, Intake& it) const {
+    __device__ void intake(int b, int, Intake& it) const {
         it.st.issue(Sin, b);
         if constexpr (FIRST) it.rows.issue(pdir, b, A_MAXMASK);
     }
@@ -854,10 +862,11 @@ struct OpLp {
         C2<T> ph[8];
         C2<T> p[8];
         C2<T> w[FIRST ? 1 : 8];
-        T V[LAST ? 8 : 1];
+        T V[FIRST ? 8 : 1];
     };
     // phi (when read) and P r (FIRST, from which load() builds the new direction) or p; the tail:
-    // what the epilogue adds, the previous passes' partial L phat (w) and V
+    // what the epilogue adds, the previous passes' partial L phat (w), or V (the first pass, along
+    // x, adds V phat: a contiguous read there rather than one more strided stream later)
     __device__ void prefetch(const Geo&, const LineCtx& lc, State& st) const {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -871,7 +880,7 @@ struct OpLp {
         for (int q = 0; q < 8; ++q) {
             const int64_t i = lc.at(q);
             if constexpr (!FIRST) st.w[q] = f.w[i];
-            if constexpr (LAST) st.V[q] = f.V[i];
+            if constexpr (FIRST) st.V[q] = f.V[i];
         }
     }
     __device__ void begin(const Geo&, int b, int blk, double* red, Scal* s, Intake& it) const {
@@ -948,11 +957,11 @@ struct OpLp {
             const int64_t i = lc.at(q);
             C2<T> o = v[q];
             if constexpr (!FIRST) o = add(o, st.w[q]);
+            if constexpr (FIRST) o = add(o, scl(st.p[q], st.V[q]));
             if constexpr (!LAST) {
                 f.w[i] = o;
             } else {
                 const C2<T> ph = st.ph[q], p = st.p[q];
-                o = add(o, scl(p, st.V[q]));
                 f.lp[i] = o;
                 // line-search sums (A = |phi|^2, B = Re conj(phi) phat, C = |phat|^2)
                 const double A = abs2(ph), Bq = redot(ph, p), Cq = abs2(p);
@@ -1148,22 +1157,22 @@ hipError_t enqueue_iteration(const IterCtx<T>& c, hipStream_t s) {
     } else if (g.dim == 2) {
         OpLp<T, 0, true, false> ox{f, dir_in, S_dir, pres, pdir};
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, pb0, s,
-                tick("dir_Lp_x", 10))) != hipSuccess)
+                tick("dir_Lp_x", 11))) != hipSuccess)
             return e;
         OpLp<T, 1, false, true> oy{f, S_dir, nullptr, none, none};
         if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, pb1, s,
-                tick("Lp_y_linesearch", 9))) != hipSuccess)
+                tick("Lp_y_linesearch", 8))) != hipSuccess)
             return e;
     } else {
         OpLp<T, 0, true, false> ox{f, dir_in, S_dir, pres, pdir};
         if ((e = launch_pass<T, 0>(g, c.B, c.tw->get(0, f64), ox, pb0, s,
-                tick("dir_Lp_x", 10))) != hipSuccess)
+                tick("dir_Lp_x", 11))) != hipSuccess)
             return e;
         OpLp<T, 1, false, false> oy{f, S_dir, nullptr, none, none};
         if ((e = launch_pass<T, 1>(g, c.B, c.tw->get(1, f64), oy, pb1, s, tick("Lp_y", 8))) != hipSuccess) return e;
         OpLp<T, 2, false, true> oz{f, S_dir, nullptr, none, none};
         if ((e = launch_pass<T, 2>(g, c.B, c.tw->get(2, f64), oz, pb2, s,
-                tick("Lp_z_linesearch", 9))) != hipSuccess)
+                tick("Lp_z_linesearch", 8))) != hipSuccess)
             return e;
     }
     (void)consumable(pbAll, R_BC, B_K, B_MAXMASK);

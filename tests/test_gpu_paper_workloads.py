@@ -129,3 +129,32 @@ def test_fast_rotation_table_cells_with_the_energy_rule(torch_gpu, eta, omega):
     assert abs(O.energy(prob, V, out) - rep["E"]) < 1e-12 * abs(rep["E"])
     r, _ = O.residual(prob, V, out)
     assert np.max(np.abs(r)) < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_fast_rotation_quartic_mixed_precision():
+    """Mixed precision (FP32 fields and transforms, FP64 scalars, FP64 refinement) on the paper's
+    fast-rotation example (quartic trap, eta = 1000, Thomas-Fermi start) at Omega = 2 and 3 on its
+    640^2 grid: both solves reach ||r||_inf <= 1e-8, and the oracle confirms the returned state
+    (norm, residual, E, lambda) and its second-order condition.  The mixed runs may end in another
+    local minimum than FP64 runs from the same start (several results are correct here), so the
+    energy is checked against the state, not against FP64.  (On 512^2 points at Omega = 3 the FP64
+    phase started from the FP32 iterate keeps sliding down a very flat valley, ||r||_inf between
+    2e-7 and 8e-5 for 3.4e4 iterations while E falls by 6e-8; that case is not part of this test.)"""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1611_02045_amd import gpe
+    states = []
+    for m, om in ((640, 2.0), (640, 3.0)):
+        prob, V, start = workload_quartic_2d(m, om, 1000.0)
+        plan = gpe.Plan.from_problem(prob, "f64")
+        phi = _to(torch, start)
+        print(f"quartic {m}^2 Omega={om:g} mixed", flush=True)
+        rep = plan.pcg_solve(_to(torch, V), phi, tol=1e-8, max_iter=100000, precision="mixed")
+        print(f"  iters {rep['iters']} (fp32 {rep['iters_fp32']}), E = {rep['E']:.10f}", flush=True)
+        assert rep["status_name"] == "ok" and rep["iters_fp32"] > 0
+        out = phi.cpu().numpy()
+        assert_state(prob, V, out, rep, 1e-8, E_rel=1e-12)
+        states.append((prob, V, out))
+    assert_local_minima(states)
