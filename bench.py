@@ -244,9 +244,11 @@ def main():
             bphi = starts0[0].to(dt).unsqueeze(0).repeat(n, 1, 1).contiguous()
             Vd = V.float() if dt == torch.complex64 else V
             rate, sec = applies_per_s(torch, pl, bphi, Vd, 10, batched=True)
-            cb = 8 if dt == torch.complex64 else 16
+            rb = 4 if dt == torch.complex64 else 8
+            # the two passes' bytes: x reads phi and the shared V once, writes W; y reads phi and W,
+            # writes H phi: (10 n + 1) s N
             out[tag] = {"applies_per_s": rate, "s_per_launch_pair": sec,
-                        "GB_s_11sN": 11 * (cb // 2) * 512 * 512 * n / sec / 1e9}
+                        "GB_s": (10 * n + 1) * rb * 512 * 512 / sec / 1e9}
             del bphi
         return out
 
@@ -597,8 +599,8 @@ def main():
         "pcg_iters_per_s_step": {"mixed": max(it_mixed) / mean(t_mixed), "fp64": max(it_fp64) / mean(t_fp64)},
         "h_applies_per_s": {"fp64": ap64, "fp32": ap32, "fp64_batch32": apb64, "fp32_batch32": apb32,
                             "fp64_graph1000": apg64, "fp32_graph1000": apg32, "at_640x640": ap640},
-        "h_apply_batch32_hbm_gbs": {
-            "fp64": 11 * 8 * 512 * 512 * batch / tb64 / 1e9, "fp32": 11 * 4 * 512 * 512 * batch / tb32 / 1e9},
+        "h_apply_batch32_hbm_gbs": {  # (10 B + 1) s N bytes: phi twice, W twice, H phi once, the shared V once
+            "fp64": (10 * batch + 1) * 8 * 512 * 512 / tb64 / 1e9, "fp32": (10 * batch + 1) * 4 * 512 * 512 / tb32 / 1e9},
         "final": {"E_mixed": [r["E"] for r in reps_mixed], "res_mixed": max(r["res_inf"] for r in reps_mixed),
                   "E_fp64": [r["E"] for r in reps_fp64], "res_fp64": max(r["res_inf"] for r in reps_fp64)},
         "kernels": {"fp32": kernel_rows(prof32), "fp64": kernel_rows(prof64)},
