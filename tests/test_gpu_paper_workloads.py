@@ -115,7 +115,9 @@ def test_fast_rotation_in_quartic_trap_512(torch_gpu):
 def test_fast_rotation_table_cells_with_the_energy_rule(torch_gpu, eta, omega):
     """Two cells of the paper's fast-rotation table on its 640^2 grid, stopped by its rule
     |E_{n+1} - E_n| <= 1e-14 (no residual test): the solve ends OK, and the oracle confirms the
-    reported energy, the unit norm and a small residual (the energy rule stops at ||r||_inf ~ 1e-5)."""
+    reported energy, the unit norm and a small residual (the energy rule stops at ||r||_inf between
+    1e-6 and 2e-5).  A self-consistency check of the returned state: the table fixes CPU times, not
+    states, so no value of the paper is compared."""
     from paper_1611_02045_amd import gpe
     torch = torch_gpu
     prob, V, start = workload_quartic_2d(640, omega, eta)
