@@ -168,6 +168,24 @@ def test_apply_H_batch32_at_512(torch_gpu, dtype):
         assert _relerr(out[b], O.hamiltonian(prob, V, phis[b])) < TOL[dtype]
 
 
+def test_apply_H_beyond_the_mall(torch_gpu):
+    """The bench's above-MALL apply configuration: 64 FP32 fields of 512^2 in one batched apply
+    (phi, H phi and the intermediate: 384 MiB); sampled instances (first, middle, last) against the
+    oracle."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob = Problem(2, (512, 512), (16.0, 16.0), 1000.0, 0.9)
+    V = harmonic_potential(prob)
+    base = random_field(prob, 23, envelope=0.02)
+    print("apply batch 64 at 512^2 f32", flush=True)
+    phis = torch.stack([_to(torch, base * (1.0 + 0.01 * k) * np.exp(0.1j * k), "f32") for k in range(64)])
+    plan = gpe.Plan.from_problem(prob, "f32")
+    out = plan.apply_H_batched(phis, _to(torch, V, "f32"))
+    for b in (0, 31, 63):
+        ref = O.hamiltonian(prob, V, phis[b].cpu().numpy().astype(np.complex128))
+        assert _relerr(out[b].cpu().numpy(), ref) < TOL["f32"]
+
+
 def test_energy_grad(torch_gpu):
     """grad_phi = 2 h^d H phi, grad_V = h^d |phi|^2, dE/dbeta, dE/domega against the oracle."""
     from paper_1611_02045_amd import gpe
