@@ -61,3 +61,33 @@ def test_noalloc_apply_rejects_a_batch_beyond_the_scratch(torch_gpu):
     assert ei.value.status == -1 and "scratch" in str(ei.value)
     torch.cuda.synchronize()
     assert bool((out == 7.0).all())  # nothing was launched
+
+
+def test_noalloc_apply_replayed_from_a_captured_graph(torch_gpu):
+    """The callers the entry point is for: a batched apply captured into a graph (on a side
+    stream) and replayed three times, with eager work and synchronisations between the replays;
+    every replay equals the eager allocating apply."""
+    from paper_1611_02045_amd import gpe
+    torch = torch_gpu
+    prob = Problem(2, (256, 256), (16.0, 16.0), 1000.0, 0.9)
+    plan = gpe.Plan.from_problem(prob, "f64")
+    phi, V = _fields(torch, prob, 4, 90, "f64")
+    ref = plan.apply_H_batched(phi, V)
+    out = torch.zeros_like(phi)
+    plan.apply_H_batched_noalloc(phi, V, out)  # first call on the device outside the capture
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            plan.apply_H_batched_noalloc(phi, V, out, stream=side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        plan.apply_H_batched(phi, V)  # eager work between the replays
+        torch.cuda.synchronize()
