@@ -92,9 +92,34 @@ int gpe_apply_H(gpe_plan_t* plan, const void* phi, const void* V, void* Hphi, vo
 int gpe_apply_H_batched(gpe_plan_t* plan, int count, const void* phi, const void* V, void* Hphi,
                         void* stream);
 
+/* Kernel choice of every H apply (gpe_apply_H, gpe_apply_H_batched, the noalloc form, and the
+ * applies inside the solvers, the backward-Euler steps and the adjoint), process-wide:
+ *   GPE_APPLY_PASSES  directional passes: an x pass (with the pointwise part) into a workspace, then
+ *                     a y pass (and a z pass) adding theirs: 11sN bytes in 2-D (s bytes per real, N
+ *                     points), 17sN in 3-D;
+ *   GPE_APPLY_PLANE   the whole-plane kernel where the xy-plane fits one workgroup's LDS (n_x, n_y
+ *                     powers of two from 32 to 256, at most 16384 points for complex64 and 8192 for
+ *                     complex128, within the device's LDS per workgroup; 128^2 complex64 needs
+ *                     147 KiB): both directions of Section 3's discrete operator in one pass over
+ *                     each plane, 5sN bytes in 2-D; in 3-D plus a z pass, 11sN.  Other grids keep
+ *                     the passes;
+ *   GPE_APPLY_AUTO    (default) the whole-plane kernel where it fits and the launch has enough
+ *                     planes to occupy the device, else the passes.
+ * Both kernels compute the same transforms and sums and agree to rounding.
+ * Meant for tests and measurements: it applies to every call in the process from the next launch
+ * on.  GPE_EINVAL for an unknown kind. */
+typedef enum { GPE_APPLY_AUTO = 0, GPE_APPLY_PASSES = 1, GPE_APPLY_PLANE = 2 } gpe_apply_kernel_t;
+int gpe_set_apply_kernel(int kind);
+
+/* The kernel (GPE_APPLY_PASSES or GPE_APPLY_PLANE) that gpe_apply_H_batched would launch for
+ * `count` fields of the plan's grid and dtype under the current setting, on the current device.
+ * kind: host, receives it. */
+int gpe_apply_kernel_for(gpe_plan_t* plan, int count, int* kind);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation): gpe_apply_H_batched without any allocation.  The
- * intermediate of its two (2-D) or three (3-D) directional passes lives in a static device array
+ * intermediate between its kernels (the running sum of the directional passes, or in 3-D the
+ * whole-plane kernel's xy-part; see gpe_set_apply_kernel) lives in a static device array
  * of GPE_NOALLOC_SCRATCH_BYTES per device, held until the process ends, instead of the plan's
  * growable workspace; the plan must have been created on the current device.  Same arguments,
  * layout and results as gpe_apply_H_batched (the same kernels run).  Requires

@@ -231,6 +231,23 @@ int gpe_apply_H(gpe_plan_t* plan, const void* phi, const void* V, void* Hphi, vo
     return gpe_apply_H_batched(plan, 1, phi, V, Hphi, stream);
 }
 
+int gpe_set_apply_kernel(int kind) {
+    if (kind < GPE_APPLY_AUTO || kind > GPE_APPLY_PLANE) {
+        set_error("unknown apply kernel kind");
+        return GPE_EINVAL;
+    }
+    set_apply_kind(kind);
+    return GPE_OK;
+}
+
+int gpe_apply_kernel_for(gpe_plan_t* plan, int count, int* kind) {
+    NEEDPTR(plan, "plan");
+    NEEDPTR(kind, "kind");
+    if (count < 1) { set_error("count must be >= 1"); return GPE_EINVAL; }
+    *kind = plane_preferred(plan->g, plan->f64(), count) ? GPE_APPLY_PLANE : GPE_APPLY_PASSES;
+    return GPE_OK;
+}
+
 int gpe_precond(gpe_plan_t* plan, int kind, const void* phi, const void* V, double alpha, const void* r, void* Pr,
                 void* stream) {
     NEEDPTR(plan, "plan");

@@ -231,21 +231,27 @@ __device__ __forceinline__ void fft_line(C2<T> (&v)[8], C2<T>* buf, const C2<T>*
 
 // fft_line for a compile-time size 2^LG (F5: 5 * 2^LG): the same stages, with every stride, offset
 // and stage count a constant (LDS addresses become immediate offsets).  WAVE: lines lie within one
-// wave.
-template <typename T, int DIR, int LG, bool WAVE, bool F5 = false>
+// wave.  CS > 0: point i of the line's LDS region sits at buf[i * CS] instead of the padded
+// buf[lpad(i)] (a column of a plane held in LDS, whose neighbouring columns go to neighbouring
+// lanes, so the stride needs no padding).
+template <typename T, int DIR, int LG, bool WAVE, bool F5 = false, int CS = 0>
 __device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<T>* tw, int t) {
     static_assert(LG >= 3 && LG <= 10, "lines of 8 to 1024 points");
     static_assert(!F5 || (LG <= 7 && !WAVE), "lines of 5 * 2^LG points: at most 640, across waves");
+    static_assert(CS == 0 || !F5, "strided regions for lines of 2^LG points only");
     constexpr int TPL = F5 ? 5 << (LG - 3) : 1 << (LG - 3);
     constexpr int REM = LG % 3;
     constexpr int N8 = LG / 3;
+    auto ix = [](int i) {
+        if constexpr (CS > 0) return i * CS; else return lpad(i);
+    };
     auto sync = [] {
         if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
     };
     auto read_back = [&] {
         sync();
 #pragma unroll
-        for (int s = 0; s < 8; ++s) v[s] = buf[lpad(t + s * TPL)];
+        for (int s = 0; s < 8; ++s) v[s] = buf[ix(t + s * TPL)];
         sync();
     };
     if constexpr (REM == 1) {
@@ -254,8 +260,8 @@ __device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = t + q * TPL;
-            buf[lpad(2 * j)] = v[q];
-            buf[lpad(2 * j + 1)] = v[q + 4];
+            buf[ix(2 * j)] = v[q];
+            buf[ix(2 * j + 1)] = v[q + 4];
         }
         read_back();
     } else if constexpr (REM == 2) {
@@ -263,8 +269,8 @@ __device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<
         dft4<T, DIR>(v[1], v[3], v[5], v[7]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            buf[lpad(4 * t + r)] = v[2 * r];
-            buf[lpad(4 * (t + TPL) + r)] = v[2 * r + 1];
+            buf[ix(4 * t + r)] = v[2 * r];
+            buf[ix(4 * (t + TPL) + r)] = v[2 * r + 1];
         }
         read_back();
     }
@@ -294,7 +300,7 @@ __device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<
         if (k + 1 < N8 || F5) {
             const int base = ((t >> lgNs) << (lgNs + 3)) + (t & (Ns - 1));
 #pragma unroll
-            for (int r = 0; r < 8; ++r) buf[lpad(base + r * Ns)] = v[r];
+            for (int r = 0; r < 8; ++r) buf[ix(base + r * Ns)] = v[r];
             if (k + 1 < N8) read_back();
         }
     }
@@ -308,7 +314,7 @@ __device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<
             if (j < P) {
                 C2<T> x[5];
 #pragma unroll
-                for (int r = 0; r < 5; ++r) x[r] = buf[lpad(j + r * P)];
+                for (int r = 0; r < 5; ++r) x[r] = buf[ix(j + r * P)];
 #pragma unroll
                 for (int r = 1; r < 5; ++r) {
                     C2<T> w = tw[j * r];
@@ -317,7 +323,7 @@ __device__ __forceinline__ void fft_line_ct(C2<T> (&v)[8], C2<T>* buf, const C2<
                 }
                 dft5<T, DIR>(x[0], x[1], x[2], x[3], x[4]);
 #pragma unroll
-                for (int r = 0; r < 5; ++r) buf[lpad(j + r * P)] = x[r];
+                for (int r = 0; r < 5; ++r) buf[ix(j + r * P)] = x[r];
             }
         }
         read_back();

@@ -69,6 +69,17 @@ hipError_t reduce_init(Reduce& r, int instances, int slots, size_t part_doubles)
 hipError_t op_apply(const Geo& g, bool f64, int B, const Twiddles& tw, const void* f, const void* V,
                     void* out, void* tmp, double beta, double omega, bool nonlinear, hipStream_t s);
 
+// Whole-plane kernel of the H apply (plane.hip): whether the grid's xy-plane fits one workgroup's
+// LDS in this dtype on the current device, whether op_apply takes it for a launch of B instances
+// (the process-wide kind set by gpe_set_apply_kernel: 0 automatic, 1 passes, 2 plane where it
+// fits), and the launch itself (out = H f in 2-D, its xy-part with the pointwise term in 3-D).
+void set_apply_kind(int kind);
+int apply_kind();
+bool plane_fits(const Geo& g, bool f64);
+bool plane_preferred(const Geo& g, bool f64, int B);
+hipError_t op_apply_plane(const Geo& g, bool f64, int B, const Twiddles& tw, const void* f, const void* V, void* out,
+                          double beta, double omega, bool nonlinear, hipStream_t s);
+
 // out = -L_z f (dim >= 2), tmp: one field of workspace.
 hipError_t op_rotation(const Geo& g, bool f64, const Twiddles& tw, const void* f, void* out, void* tmp, hipStream_t s);
 // Interpolation of one field on the grid g onto the grid with twice the points per axis (out:

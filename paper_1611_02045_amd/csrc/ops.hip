@@ -88,6 +88,13 @@ static hipError_t apply_t(const Geo& g, int B, const Twiddles& tw, const void* f
         OpApply<T, 0> op{F, nullptr, (C2<T>*)out, (const T*)V, beta, omega, 1, nl};
         return launch_pass<T, 0>(g, B, tw.get(0, f64), op, none, s);
     }
+    if (plane_preferred(g, f64, B)) {
+        // whole xy-planes in LDS: all of H f in 2-D; in 3-D the xy-part into tmp, then the z pass
+        if (g.dim == 2) return op_apply_plane(g, f64, B, tw, f, V, out, beta, omega, nl, s);
+        if ((e = op_apply_plane(g, f64, B, tw, f, V, tmp, beta, omega, nl, s)) != hipSuccess) return e;
+        OpApply<T, 2> oz{F, (const C2<T>*)tmp, (C2<T>*)out, nullptr, beta, omega, 0, nl};
+        return launch_pass<T, 2>(g, B, tw.get(2, f64), oz, none, s);
+    }
     // x-pass (with the pointwise part) into tmp, then the y (and z) passes accumulate.
     OpApply<T, 0> ox{F, nullptr, (C2<T>*)tmp, (const T*)V, beta, omega, 1, nl};
     if ((e = launch_pass<T, 0>(g, B, tw.get(0, f64), ox, none, s)) != hipSuccess) return e;

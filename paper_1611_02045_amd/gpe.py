@@ -63,6 +63,8 @@ SIGNATURES = {
     "gpe_apply_H": (_I, [_VP, _VP, _VP, _VP, _VP]),
     "gpe_apply_H_batched": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
     "gpe_apply_H_batched_noalloc": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
+    "gpe_set_apply_kernel": (_I, [_I]),
+    "gpe_apply_kernel_for": (_I, [_VP, _I, ctypes.POINTER(_I)]),
     "gpe_precond": (_I, [_VP, _I, _VP, _VP, _D, _VP, _VP, _VP]),
     "gpe_pcg_opts_default": (None, [ctypes.POINTER(PcgOpts)]),
     "gpe_pcg_solve": (_I, [_VP, _VP, _VP, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgReport), _VP]),
@@ -115,6 +117,18 @@ def _stream(stream=None):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+APPLY_KERNELS = {0: "auto", 1: "passes", 2: "plane"}
+
+
+def set_apply_kernel(kind: str) -> None:
+    """gpe_set_apply_kernel: "auto" (default), "passes" or "plane" for every H apply of the
+    process from the next launch on."""
+    codes = {v: k for k, v in APPLY_KERNELS.items()}
+    if kind not in codes:
+        raise ValueError(f"unknown apply kernel {kind!r}")
+    _check(lib().gpe_set_apply_kernel(codes[kind]))
 
 
 def make_problem(dim: int, n, L, beta: float, omega: float) -> Problem:
@@ -237,6 +251,12 @@ class Plan:
                                                  self._field(V, "V", False), self._field(out, "out", batch=count),
                                                  _stream(stream)))
         return out
+
+    def apply_kernel_for(self, count: int = 1) -> str:
+        """gpe_apply_kernel_for: "plane" or "passes", the kernel an apply of `count` fields runs."""
+        k = _I()
+        _check(lib().gpe_apply_kernel_for(self._h, int(count), ctypes.byref(k)))
+        return APPLY_KERNELS[k.value]
 
     def autotune(self, count: int = 1, stream=None):
         """Measure and record the fastest lines per workgroup of each axis's pass for batches of

@@ -146,3 +146,16 @@ def test_invalid_nested_and_be_arguments_are_rejected_on_the_host(gpe):
 def test_autotune_rejects_bad_arguments(gpe):
     L = gpe.lib()
     assert L.gpe_autotune(None, 1, None, None, None) == -1
+
+
+def test_apply_kernel_choice_is_validated_on_the_host(gpe):
+    L = gpe.lib()
+    for bad in (-1, 3, 99):
+        assert L.gpe_set_apply_kernel(bad) == -1
+        assert b"kind" in L.gpe_last_error()
+    for kind in ("passes", "plane", "auto"):
+        gpe.set_apply_kernel(kind)
+    with pytest.raises(ValueError):
+        gpe.set_apply_kernel("fused")
+    k = ctypes.c_int(-5)
+    assert L.gpe_apply_kernel_for(None, 1, ctypes.byref(k)) == -1 and k.value == -5
