@@ -201,6 +201,9 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=30)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-kernel profile of the step's iteration and a 512 MiB copy (counter runs)")
+    ap.add_argument("--profile-plane", action="store_true",
+                    help="only the whole-plane and directional-pass H applies of the plane comparison, 5 "
+                         "launches each (profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver is a single-GPU "
@@ -251,6 +254,63 @@ def main():
                         "GB_s": (10 * n + 1) * rb * 512 * 512 / sec / 1e9}
             del bphi
         return out
+
+    def plane_rates(reps=20, profile_run=False):
+        """The whole-plane H apply against the directional passes (both forced through
+        gpe_set_apply_kernel) on planes that fit one workgroup's LDS: 128^2 complex64 (one CU per
+        plane) for 1, 256 and 1024 fields, 64^2 complex128 for 1 and 1024 fields, and 3-D 128^3
+        complex64 (128 planes per field, then the z pass) for 2 fields.  Seconds per launch from
+        torch events around `reps` launches on the current stream (the applies' stream); bytes per
+        field as the two kernels move them: 2-D 5sN (plane) and 11sN (passes), 3-D 11sN and 17sN,
+        with the shared V counted once per launch."""
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(2024)
+        res = {}
+        for dim, n, dt, counts in ((2, (128, 128), "f32", (1, 256, 1024)), (2, (64, 64), "f64", (1, 1024)),
+                                   (3, (128, 128, 128), "f32", (2,))):
+            pp = type(prob)(dim, n, tuple(8.0 for _ in n), 1000.0, 0.9)
+            pl = gpe.Plan.from_problem(pp, dt)
+            cd, rd, sb = (torch.complex64, torch.float32, 4) if dt == "f32" else (torch.complex128, torch.float64, 8)
+            shape = tuple(reversed(n))
+            Vd = torch.rand(shape, dtype=rd, device="cuda", generator=gen)
+            npts = 1
+            for m in n:
+                npts *= m
+            for cnt in counts:
+                ph = torch.randn((cnt,) + shape, dtype=cd, device="cuda", generator=gen)
+                o = torch.empty_like(ph)
+                row = {"auto": pl.apply_kernel_for(cnt)}
+                for kind in ("plane", "passes"):
+                    gpe.set_apply_kernel(kind)
+                    try:
+                        for _ in range(3):
+                            pl.apply_H_batched(ph, Vd, o)
+                        torch.cuda.synchronize()
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        r = 5 if profile_run else reps
+                        e0.record()
+                        for _ in range(r):
+                            pl.apply_H_batched(ph, Vd, o)
+                        e1.record()
+                        torch.cuda.synchronize()
+                    finally:
+                        gpe.set_apply_kernel("auto")
+                    sec = e0.elapsed_time(e1) * 1e-3 / r
+                    per = (5 if dim == 2 else 11) if kind == "plane" else (11 if dim == 2 else 17)
+                    nbytes = ((per - 1) * cnt + 1) * sb * npts
+                    row[kind] = {"us": sec * 1e6, "GB_s": nbytes / sec / 1e9, "bytes": nbytes}
+                row["speedup_plane"] = row["passes"]["us"] / row["plane"]["us"]
+                res[f"{'x'.join(map(str, n))}_{dt}_x{cnt}"] = row
+                del ph, o
+        return res
+
+    if args.profile_plane:
+        rates = plane_rates(profile_run=True)
+        a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)  # counter scale
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_plane": True, "copy_bytes": a.numel(), "rates": rates}), flush=True)
+        return
 
     if args.profile_only:
         for prec in ("mixed", "fp64"):  # first launches load the kernels: keep them out of the averages
@@ -520,6 +580,10 @@ def main():
             ap640[dt], _ = applies_per_s(torch, pl, torch.from_numpy(fq).to("cuda", cd),
                                          torch.from_numpy(Vq).to("cuda", rd), 400)
         log(f"[bench] H applies at 640^2: {ap640}")
+    log("[bench] whole-plane H apply against the passes")
+    planes = plane_rates()
+    log("[bench] whole-plane: " + ", ".join(f"{k}: {v['plane']['us']:.1f} us vs {v['passes']['us']:.1f} us"
+                                             for k, v in planes.items()))
     apg64 = apg32 = None
     try:
         apg64 = applies_per_s_graph(torch, plan64, phi0, V)
@@ -599,6 +663,7 @@ def main():
         "pcg_iters_per_s_step": {"mixed": max(it_mixed) / mean(t_mixed), "fp64": max(it_fp64) / mean(t_fp64)},
         "h_applies_per_s": {"fp64": ap64, "fp32": ap32, "fp64_batch32": apb64, "fp32_batch32": apb32,
                             "fp64_graph1000": apg64, "fp32_graph1000": apg32, "at_640x640": ap640},
+        "h_apply_whole_plane": planes,
         "h_apply_batch32_hbm_gbs": {  # (10 B + 1) s N bytes: phi twice, W twice, H phi once, the shared V once
             "fp64": (10 * batch + 1) * 8 * 512 * 512 / tb64 / 1e9, "fp32": (10 * batch + 1) * 4 * 512 * 512 / tb32 / 1e9},
         "final": {"E_mixed": [r["E"] for r in reps_mixed], "res_mixed": max(r["res_inf"] for r in reps_mixed),
