@@ -27,13 +27,14 @@ paper states (Sections 4, 5.2, 5.5) or the paper's printed energies, except:
   * the exact iteration trajectory of PCG at Omega > 0, whose iteration counts the paper only
     shows in figures that are not available (parity unpinned for trajectories; final states
     are pinned);
-  * two constants of the potential preconditioner, the shift alpha_V = lambda~ and the factor
-    eta (not eta/2) of |phi|^2 in its diagonal: definitional (eq. PV with the adaptive shift),
-    checked by reading (parity unpinned); that V enters the diagonal is pinned by the Section
-    5.5 scaling of kappa_V;
-  * the term Re<r_{n-1}, P_n r_n> of the Polak-Ribiere coefficient: it vanishes on the
-    quadratic model whose conjugate-gradient rate pins the rest of the coefficient
-    (parity unpinned for that term).
+  * the shift of the potential preconditioner, alpha_V = lambda~: definitional (eq. PV with the
+    adaptive shift of Section 5.5), checked by reading (parity unpinned).  Its diagonal
+    V + eta |phi|^2 is pinned: it equals the multiplicative part of H_phi (on constant fields,
+    where T and L_z vanish, H_phi phi = (V + eta |phi|^2) phi), and the Section 5.5 scaling of
+    kappa_V needs the V in it.
+The Polak-Ribiere coefficient is pinned by the properties that set it apart (it vanishes when the
+residual repeats, the automatic restart; it equals Fletcher-Reeves for P-orthogonal successive
+residuals; it is cut at zero) and by the conjugate-gradient contraction rate.
 """
 from __future__ import annotations
 
@@ -428,6 +429,18 @@ class SolveResult:
     history: list = field(default_factory=list)
 
 
+def cg_coefficient(prob, r, Pr, r_prev, rPr_prev: float, rule: str = "pr") -> float:
+    """The conjugate-gradient coefficient of Section 5.2 (eq. CG:PR) from the current residual r_n,
+    its preconditioned form P_n r_n, the previous residual r_{n-1} and the stored
+    <r_{n-1}, P_{n-1} r_{n-1}>: Polak-Ribiere, kept non-negative,
+    max((<r_n, P_n r_n> - Re<r_{n-1}, P_n r_n>) / <r_{n-1}, P_{n-1} r_{n-1}>, 0), or with
+    rule="fr" the Fletcher-Reeves ratio <r_n, P_n r_n> / <r_{n-1}, P_{n-1} r_{n-1}>."""
+    rPr = inner(prob, r, Pr).real
+    if rule == "fr":
+        return rPr / rPr_prev
+    return max((rPr - inner(prob, r_prev, Pr).real) / rPr_prev, 0.0)
+
+
 def pcg(prob, V, phi0, *, method: str = "pcg", precond: str = "combined", tol_res: float = 1e-8,
         tol_energy: float = 0.0, max_iter: int = 10_000, theta_default: float = 0.1,
         max_halvings: int = 30, beta_rule: str = "pr", line_search: str = "heuristic",
@@ -490,10 +503,7 @@ def pcg(prob, V, phi0, *, method: str = "pcg", precond: str = "combined", tol_re
         # CG coefficient (Section 5.2)
         beta = 0.0
         if method == "pcg" and p_prev is not None and rPr_prev > 0.0:
-            if beta_rule == "fr":
-                beta = rPr / rPr_prev
-            else:
-                beta = max((rPr - inner(prob, r_prev, Pr).real) / rPr_prev, 0.0)
+            beta = cg_coefficient(prob, r, Pr, r_prev, rPr_prev, beta_rule)
         d = -Pr + beta * p_prev if beta != 0.0 else -Pr
         p = project(prob, phi, d)
         restarted = False

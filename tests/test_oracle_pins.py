@@ -347,6 +347,63 @@ def test_combined_preconditioner_composition():
     assert a > 0
 
 
+@pytest.mark.parametrize("dim,n,L,beta,omega", [(1, (32,), (6.0,), 300.0, 0.0),
+                                                (2, (16, 8), (4.0, 3.0), 150.0, 0.8),
+                                                (3, (8, 8, 4), (3.0, 3.0, 2.0), 80.0, 0.5)])
+def test_potential_preconditioner_inverts_the_pointwise_hamiltonian(dim, n, L, beta, omega):
+    """P_V^{-1} = alpha + V + eta |phi|^2 is the shifted multiplicative part of H_phi (Section 5.5):
+    on a constant unit-norm field T and L_z vanish, so H_phi phi / phi is V + eta |phi|^2 pointwise;
+    a dropped V, an eta/2 or a missing shift fails."""
+    prob = Problem(dim, n, L, beta, omega)
+    rng = np.random.default_rng(3)
+    V = harmonic_potential(prob) + rng.uniform(0.0, 2.0, prob.shape)
+    c = np.full(prob.shape, 1.0 / math.sqrt(math.prod(2.0 * a for a in L)), dtype=np.complex128) * np.exp(0.3j)
+    assert abs(O.norm(prob, c) - 1.0) < 1e-14
+    pointwise = (O.hamiltonian(prob, V, c) / c).real
+    for alpha in (0.0, 2.5):
+        np.testing.assert_allclose(O.potential_diagonal(prob, V, c, alpha), alpha + pointwise, rtol=1e-12)
+
+
+def _pr_inputs(seed):
+    prob = Problem(2, (16, 16), (4.0, 4.0), 100.0, 0.6)
+    V = harmonic_potential(prob)
+    phi = random_field(prob, seed)
+    phi /= O.norm(prob, phi)
+    r, _ = O.residual(prob, V, phi)
+    Pr = O.apply_preconditioner(prob, "combined", V, phi, r)
+    return prob, V, phi, r, Pr
+
+
+def test_polak_ribiere_restarts_when_the_residual_repeats():
+    """Polak-Ribiere's automatic restart (Section 5.2; the reason it is preferred to
+    Fletcher-Reeves): when r_n = r_{n-1} the coefficient is 0, where Fletcher-Reeves gives 1; when
+    the new residual overshoots (r_{n-1} = 2 r_n) the raw ratio is negative and is cut to 0."""
+    prob, V, phi, r, Pr = _pr_inputs(11)
+    rPr = O.inner(prob, r, Pr).real
+    assert rPr > 0
+    assert abs(O.cg_coefficient(prob, r, Pr, r, rPr, "pr")) < 1e-14
+    assert abs(O.cg_coefficient(prob, r, Pr, r, rPr, "fr") - 1.0) < 1e-14
+    assert O.cg_coefficient(prob, r, Pr, 2.0 * r, 4.0 * rPr, "pr") == 0.0
+
+
+def test_polak_ribiere_equals_fletcher_reeves_for_orthogonal_residuals():
+    """When successive residuals are orthogonal in the P_n inner product (as in linear conjugate
+    gradients), the Polak-Ribiere and Fletcher-Reeves coefficients coincide; otherwise they differ
+    by Re<r_{n-1}, P_n r_n> / <r_{n-1}, P_{n-1} r_{n-1}>."""
+    prob, V, phi, r, Pr = _pr_inputs(12)
+    rPr = O.inner(prob, r, Pr).real
+    g = random_field(prob, 13)
+    r_prev = g - (O.inner(prob, g, Pr).real / rPr) * r
+    assert abs(O.inner(prob, r_prev, Pr).real) < 1e-12 * O.norm(prob, r_prev) * O.norm(prob, Pr)
+    denom = 0.7 * rPr
+    pr = O.cg_coefficient(prob, r, Pr, r_prev, denom, "pr")
+    fr = O.cg_coefficient(prob, r, Pr, r_prev, denom, "fr")
+    assert abs(pr - fr) < 1e-12 * fr
+    # a residual tilted towards r_n: the coefficient drops by exactly the overlap
+    tilt = r_prev + 0.25 * r
+    assert abs(O.cg_coefficient(prob, r, Pr, tilt, denom, "pr") - 0.75 * fr) < 1e-12 * fr
+
+
 def test_preconditioner_rejects_non_positive_shift():
     prob = Problem(1, (16,), (4.0,), 1.0, 0.0)
     V = -harmonic_potential(prob) - 100.0
