@@ -159,3 +159,43 @@ def test_automatic_kernel_choice(torch_gpu):
     assert big.apply_kernel_for(cus) == "plane"
     assert cube.apply_kernel_for(1) == ("plane" if 128 >= cus else "passes")
     assert cube.apply_kernel_for(-(-cus // 128)) == "plane"
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_solvers_with_either_apply_kernel(torch_gpu, dtype):
+    """The solvers' own H applies (L phi refreshes, the final FP64 check, the backward-Euler inner
+    operator) run through whichever kernel is set: a 64^2 rotating problem solved by PCG and
+    advanced by backward-Euler steps with the plane kernel and with the passes reaches the same
+    state (energy and the oracle's residual) either way."""
+    from paper_1611_02045_amd import gpe
+    from conftest import residual_bound
+    torch = torch_gpu
+    prob = Problem(2, (64, 64), (8.0, 8.0), 200.0, 0.4)
+    V = harmonic_potential(prob)
+    phi0 = random_field(prob, 9, envelope=0.08)
+    plan = gpe.Plan.from_problem(prob, dtype)
+    tol = 1e-8 if dtype == "f64" else 1e-4
+    out = {}
+    try:
+        for kind in ("plane", "passes"):
+            gpe.set_apply_kernel(kind)
+            assert plan.apply_kernel_for(1) == kind
+            phi = _to(torch, phi0, dtype)
+            rep = plan.pcg_solve(_to(torch, V, dtype), phi, tol=tol, max_iter=20000)
+            assert rep["status"] == 0, (kind, rep)
+            be = phi.clone()
+            rb = plan.be_solve(_to(torch, V, dtype), be, 0.05, inner_tol=1e-10, tol=1e-300, max_iter=3)
+            out[kind] = (rep, phi.cpu().numpy(), rb, be.cpu().numpy())
+            print(f"  {kind}: {rep['iters']} iterations, E = {rep['E']:.12f}, BE E = {rb['E']:.12f}", flush=True)
+    finally:
+        gpe.set_apply_kernel("auto")
+    (ra, pa, ba, bea), (rp, pp, bp, bep) = out["plane"], out["passes"]
+    e_tol = 1e-9 if dtype == "f64" else 1e-5
+    assert abs(ra["E"] - rp["E"]) < e_tol * abs(rp["E"])
+    for rep, phi in ((ra, pa), (rp, pp)):
+        r, lam = O.residual(prob, V, phi.astype(np.complex128) / O.norm(prob, phi.astype(np.complex128)))
+        if dtype == "f64":
+            assert float(np.max(np.abs(r))) <= residual_bound(tol)
+        assert abs(lam - rep["lam"]) < (1e-9 if dtype == "f64" else 1e-4) * abs(lam)
+    # three backward-Euler steps from each converged state stay at it (energies agree)
+    assert abs(ba["E"] - bp["E"]) < e_tol * abs(bp["E"])
