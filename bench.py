@@ -622,6 +622,23 @@ def main():
                     "iteration": big["iteration_fp32_x24"], "fp64_iteration_x8": kernel_rows(prof64),
                     "applies": {k: v for k, v in big.items() if k.startswith("apply")}}
 
+    # the same measurements as fractions of the HBM peak: an iteration of the step's configuration as the
+    # sum of its passes' bytes over the sum of their kernel times, and the batched H applies
+    def iteration_frac(rows):
+        by = sum(r["bytes"] for r in rows)
+        sec = sum(r["avg_ms"] for r in rows) * 1e-3
+        return {"bytes": by, "us": sec * 1e6, "GB_s": by / sec / 1e9, "frac": by / sec / 1e9 / HBM_PEAK_GBS}
+    hbm_fractions = {
+        "pcg_iteration_fp32_x8": iteration_frac(kernel_rows(prof32)),
+        "pcg_iteration_fp64_x8": iteration_frac(kernel_rows(prof64)),
+        "pcg_iteration_fp32_x24_beyond_mall": iteration_frac(big["iteration_fp32_x24"]),
+        "h_apply_fp32_x64_beyond_mall": big["apply_fp32_x64"]["GB_s"] / HBM_PEAK_GBS,
+        "h_apply_fp64_x32_beyond_mall": big["apply_fp64_x32"]["GB_s"] / HBM_PEAK_GBS,
+        "h_apply_fp32_x32": (10 * batch + 1) * 4 * 512 * 512 / tb32 / 1e9 / HBM_PEAK_GBS,
+        "h_apply_fp64_x32": (10 * batch + 1) * 8 * 512 * 512 / tb64 / 1e9 / HBM_PEAK_GBS,
+        "h_apply_whole_plane_128x128_fp32_x1024": planes["128x128_f32_x1024"]["plane"]["GB_s"] / HBM_PEAK_GBS,
+    }
+
     it_fp64_single = single["fp64"]["iters"] if single else [r["iters"] for r in reps_fp64]
     cpu = None
     if not args.no_cpu:
@@ -669,6 +686,7 @@ def main():
         "final": {"E_mixed": [r["E"] for r in reps_mixed], "res_mixed": max(r["res_inf"] for r in reps_mixed),
                   "E_fp64": [r["E"] for r in reps_fp64], "res_fp64": max(r["res_inf"] for r in reps_fp64)},
         "kernels": {"fp32": kernel_rows(prof32), "fp64": kernel_rows(prof64)},
+        "hbm_peak_fractions": hbm_fractions,
         "roofline": roofline,
         "roofline_above_mall": roofline_big,
         "cpu_baseline": cpu,
