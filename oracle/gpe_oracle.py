@@ -24,9 +24,11 @@ Arrays use numpy shape (n_x,), (n_y, n_x) or (n_z, n_y, n_x): axis a lives on nu
 Parity status: every function here is pinned by a CPU test against closed forms, brute-force
 sums, library eigensolvers, finite differences, the asymptotic rates and condition numbers the
 paper states (Sections 4, 5.2, 5.5) or the paper's printed energies, except:
-  * the exact iteration trajectory of PCG at Omega > 0, whose iteration counts the paper only
-    shows in figures that are not available (parity unpinned for trajectories; final states
-    are pinned);
+  * the iteration-by-iteration trajectory of PCG at Omega > 0: the paper shows its iteration
+    counts only in figures that are not available, so no external value fixes it (parity
+    unpinned for trajectories).  pcg itself is pinned through its results: the paper's printed
+    energies, the exact beta = 0 ground states, the dense eigensolver, the conjugate-gradient
+    contraction rate, energy decrease and norm conservation along the iterates;
   * the shift of the potential preconditioner, alpha_V = lambda~: definitional (eq. PV with the
     adaptive shift of Section 5.5), checked by reading (parity unpinned).  Its diagonal
     V + eta |phi|^2 is pinned: it equals the multiplicative part of H_phi (on constant fields,
