@@ -131,6 +131,57 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def _oracle_sample_job(args):
+    """One worker of the all-cores oracle sample: `iters` FP64 PCG_C iterations from one start (BLAS
+    and OpenMP held to one thread per process)."""
+    sys.path.insert(0, ROOT)
+    from oracle import gpe_oracle as O
+    prob, V, phi0, iters = args
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        pass
+    t0 = time.perf_counter()
+    res = O.pcg(prob, V, phi0, tol_res=1e-8, max_iter=iters)
+    return max(1, res.iters), time.perf_counter() - t0
+
+
+def cpu_all_cores(prob, V, starts, iters, gpu_fp64_iters):
+    """The oracle on the host's cores: the eight starts in concurrent worker processes, one start each
+    (at most as many as the cores this process may use, 16 at most), `iters` iterations each; the step
+    extrapolated as the starts solved concurrently (the slowest start's GPU FP64 iteration count at the
+    measured per-process rate)."""
+    import multiprocessing as mp
+    import os
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    procs = max(1, min(len(starts), avail, 16))
+    jobs = [(prob, V, starts[k], iters) for k in range(procs)]
+    ctx = mp.get_context("spawn")
+    # the workers inherit one BLAS / OpenMP thread each (set before they start: numpy reads it on import)
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"
+    try:
+        t0 = time.perf_counter()
+        with ctx.Pool(procs) as pool:
+            out = pool.map(_oracle_sample_job, jobs)
+        wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    per_proc = [n / sec for n, sec in out]
+    rate = min(per_proc)
+    return {"processes": procs, "cores_available": avail, "iters_each": iters,
+            "iters_per_s_total": sum(n for n, _ in out) / wall, "iters_per_s_per_process": rate,
+            "step_s": max(gpu_fp64_iters[:procs]) / rate if procs == len(starts) else None,
+            "note": "each start on its own process; the step extrapolated as the starts solved concurrently"}
+
+
 def cpu_baseline(prob, V, phi0, iters, gpu_fp64_iters_total):
     """The FP64 oracle, as it stands, on the GPU machine's host: PCG iterations/s and H_phi applies/s on
     the 512^2 workload (bounded samples), the 1-D 256-point configuration solved to 1e-10 and the
@@ -612,6 +663,23 @@ def main():
                 "timing": f"HIP start/stop events recorded by each launch (kernel execution only), {S} instances",
                 "cache": "the step's working set (8 FP32 instances, ~136 MiB) fits in the 256 MB MALL: "
                          "see roofline_above_mall for the same kernel with a DRAM-sized working set"}
+    # a streaming kernel of known size as a second denominator: torch's elementwise kernel reading and
+    # writing 1 GiB of FP32 (beyond the MALL)
+    ca = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        torch.mul(ca, 1.0, out=cb)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.mul(ca, 1.0, out=cb)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * ca.numel() * 4 / (e0.elapsed_time(e1) * 1e-3 / 10) / 1e9
+    del ca, cb
+    roofline["copy_GB_s"] = copy_gbs
+    roofline["frac_of_copy"] = achieved / copy_gbs
     log("[bench] above-MALL profile")
     big = above_mall()
     row = next(r for r in big["iteration_fp32_x24"] if r["name"] == name)
@@ -620,7 +688,8 @@ def main():
                     "kernel": f"{name} (fp32)", "instances": 3 * S, "bytes_per_launch": row["bytes"],
                     "avg_ms": row["avg_ms"], "working_set_MiB": 3 * S * (8 * 8 + 4) * 512 * 512 / 2 ** 20,
                     "iteration": big["iteration_fp32_x24"], "fp64_iteration_x8": kernel_rows(prof64),
-                    "applies": {k: v for k, v in big.items() if k.startswith("apply")}}
+                    "applies": {k: v for k, v in big.items() if k.startswith("apply")},
+                    "copy_GB_s": copy_gbs, "frac_of_copy": row["GB_s"] / copy_gbs}
 
     # the same measurements as fractions of the HBM peak: an iteration of the step's configuration as the
     # sum of its passes' bytes over the sum of their kernel times, and the batched H applies
@@ -644,6 +713,8 @@ def main():
     if not args.no_cpu:
         log(f"[bench] CPU oracle sample ({args.cpu_iters} iterations)")
         cpu = cpu_baseline(prob, V_np, starts_np[0], args.cpu_iters, int(sum(it_fp64_single)))
+        log("[bench] CPU oracle sample on all cores")
+        cpu["all_cores"] = cpu_all_cores(prob, V_np, starts_np, args.cpu_iters, it_fp64_single)
 
     it_mixed = [r["iters"] for r in reps_mixed]
     it_fp64 = [r["iters"] for r in reps_fp64]
