@@ -9,7 +9,9 @@
 //   y phase   columns of phi come from global memory into registers, 8 points per thread; each is
 //             transformed along y with the column's own LDS slots as the exchange buffer,
 //             multiplied by sigma_y = mu^2/2 - omega x mu (x of the column), transformed back and
-//             left in its slots.
+//             left in its slots.  128-point columns of a workgroup with 8 threads per column take 16
+//             points per thread instead: all columns in one round, a radix-16 stage in registers and
+//             one exchange per transform (fft128_col16).
 //   x phase   each row's y-part is taken from the plane into registers and the row's slots become
 //             the exchange buffer of its x transform (sigma_x = xi^2/2 + omega y xi); phi's row is
 //             read a second time (a cache hit: the workgroup read it moments before) for the
@@ -34,6 +36,12 @@
 namespace gpe {
 
 template <typename T, int LGX, int LGY>
+struct PlaneCfg;
+// whether the y phase takes 128-point columns 16 points per thread, all columns in one round
+template <class P, int LGY>
+constexpr bool kCol16 = LGY == 7 && P::NX * 8 == P::W;
+
+template <typename T, int LGX, int LGY>
 struct PlaneCfg {
     static constexpr int NX = 1 << LGX, NY = 1 << LGY, NP = NX * NY;
     static constexpr int WMAX = sizeof(T) == 4 ? 1024 : 512;  // threads: registers per lane vs waves
@@ -47,6 +55,69 @@ struct PlaneCfg {
     // supported: 32..256 points per axis, at most 16384 points (8192 for complex128)
     static constexpr bool OK = LGX >= 5 && LGX <= 8 && LGY >= 5 && LGY <= 8 && NP <= (sizeof(T) == 4 ? 16384 : 8192);
 };
+
+// 16-point DFT in place, y_k = sum_s v_s e^{DIR 2 pi i s k / 16}, as 4 x 4: DFTs over a of v[4a + b],
+// the twiddles e^{DIR 2 pi i b c / 16}, DFTs over b.  Output y_{c + 4d} is left in v[d + 4c].
+template <typename T, int DIR>
+__device__ __forceinline__ void dft16_t(C2<T> (&v)[16]) {
+    const T c1 = (T)0.923879532511286756128183189396788933;  // cos(pi/8)
+    const T s1 = (T)0.382683432365089771728459984030398866;  // sin(pi/8)
+    const T h = (T)0.707106781186547524400844362104849039;   // cos(pi/4)
+    const T d = (T)DIR;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dft4<T, DIR>(v[b], v[4 + b], v[8 + b], v[12 + b]);  // v[b + 4c] = z_bc
+    v[5] = mul(v[5], mk(c1, d * s1));     // b = 1, c = 1: e^{DIR i pi/8}
+    v[9] = mul(v[9], mk(h, d * h));       // b = 1, c = 2: e^{DIR i pi/4}
+    v[13] = mul(v[13], mk(s1, d * c1));   // b = 1, c = 3: e^{DIR 3 i pi/8}
+    v[6] = mul(v[6], mk(h, d * h));       // b = 2, c = 1
+    v[10] = rot90<T, DIR>(v[10]);         // b = 2, c = 2: e^{DIR i pi/2}
+    v[14] = mul(v[14], mk(-h, d * h));    // b = 2, c = 3: e^{DIR 3 i pi/4}
+    v[7] = mul(v[7], mk(s1, d * c1));     // b = 3, c = 1
+    v[11] = mul(v[11], mk(-h, d * h));    // b = 3, c = 2
+    v[15] = mul(v[15], mk(-c1, -d * s1)); // b = 3, c = 3: e^{DIR 9 i pi/8}
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dft4<T, DIR>(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+}
+
+// A 128-point column held as 16 points per thread: thread t of the column's 8 keeps positions
+// t + 8s (s = 0..15).  A radix-16 stage in registers (butterfly t: positions t + 8s), one exchange
+// through the column's LDS slots (point i at buf[i * CS]), then a radix-8 stage (Ns = 16) whose two
+// butterflies per thread, t and t + 8, read exactly the thread's own positions again and leave
+// X[t + 8s] in v[s]: one exchange per transform.  tw: the 128-entry table e^{-2 pi i e / 128}.
+template <typename T, int DIR, int CS>
+__device__ __forceinline__ void fft128_col16(C2<T> (&v)[16], C2<T>* buf, const C2<T>* tw, int t) {
+    dft16_t<T, DIR>(v);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) buf[(16 * t + k) * CS] = v[(k >> 2) + 4 * (k & 3)];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) v[s] = buf[(t + 8 * s) * CS];
+    __syncthreads();
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int j = t + 8 * half;  // butterfly: positions j + 16 r, twiddles e^{DIR 2 pi i j r / 128}
+        C2<T> e[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) e[r] = v[2 * r + half];
+        C2<T> w1 = tw[j], w2 = tw[2 * j], w4 = tw[4 * j];
+        if (DIR > 0) {
+            w1.y = -w1.y;
+            w2.y = -w2.y;
+            w4.y = -w4.y;
+        }
+        const C2<T> w3 = mul(w1, w2);
+        e[1] = mul(e[1], w1);
+        e[2] = mul(e[2], w2);
+        e[3] = mul(e[3], w3);
+        e[4] = mul(e[4], w4);
+        e[5] = mul(e[5], mul(w1, w4));
+        e[6] = mul(e[6], mul(w2, w4));
+        e[7] = mul(e[7], mul(w3, w4));
+        dft8<T, DIR>(e);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[2 * r + half] = e[r];
+    }
+}
 
 template <typename T, int LGX, int LGY>
 __global__ __launch_bounds__((PlaneCfg<T, LGX, LGY>::W)) void plane_apply_kernel(
@@ -67,11 +138,33 @@ __global__ __launch_bounds__((PlaneCfg<T, LGX, LGY>::W)) void plane_apply_kernel
     const bool rot = g.dim >= 2 && omega != 0.0;
     const double kin = 1.0;
 
-    // y phase: thread ty of column cy (+ ry * CY).  Columns come straight from global memory (a
-    // wave reads one row segment of 64 adjacent columns), the first round's in one round trip
-    // with the twiddle tables.
-    const int cy = tid % P::CY, ty = tid / P::CY;
+    // y phase.  Columns come straight from global memory (a wave reads one row segment of 64
+    // adjacent columns), the first round's in one round trip with the twiddle tables.
     C2<T> v[8];
+    if constexpr (kCol16<P, LGY>) {
+        // 128-point columns, all at once: 16 points per thread, one exchange per transform
+        const int col = tid % P::NX, t = tid / P::NX;
+        C2<T> u[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) u[s] = fp[(int64_t)(t + 8 * s) * P::NX + col];
+        for (int i = tid; i < P::NX; i += P::W) twx[i] = twx_g[i];
+        for (int i = tid; i < P::NY; i += P::W) twy[i] = twy_g[i];
+        __syncthreads();
+        C2<T>* cbuf = plane + lpad(col);
+        fft128_col16<T, -1, P::RS>(u, cbuf, twy, t);
+        const double rc = rot ? -omega * coord_of(col, g.L[0], g.h[0]) : 0.0;
+        const double inv = 1.0 / P::NY;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const double mu = freq_of(t + 8 * s, P::NY, g.dk[1]);
+            u[s] = scl(u[s], (T)((0.5 * kin * mu * mu + rc * mu) * inv));
+        }
+        fft128_col16<T, +1, P::RS>(u, cbuf, twy, t);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) cbuf[(t + 8 * s) * P::RS] = u[s];
+    } else {
+    // thread ty of column cy (+ ry * CY)
+    const int cy = tid % P::CY, ty = tid / P::CY;
     auto load_col = [&](int col) {
 #pragma unroll
         for (int s = 0; s < 8; ++s) v[s] = fp[(int64_t)(ty + s * P::TY) * P::NX + col];
@@ -97,6 +190,7 @@ __global__ __launch_bounds__((PlaneCfg<T, LGX, LGY>::W)) void plane_apply_kernel
         // the transform's last exchange ended with a barrier: the slots are free
 #pragma unroll
         for (int s = 0; s < 8; ++s) cbuf[(ty + s * P::TY) * P::RS] = v[s];
+    }
     }
     __syncthreads();  // the y-part is complete in the plane
 
