@@ -252,6 +252,9 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=30)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-kernel profile of the step's iteration and a 512 MiB copy (counter runs)")
+    ap.add_argument("--profile-more", action="store_true",
+                    help="only the per-kernel profiles of the 3-D 128^3 iteration and of the sweep's grid groups "
+                         "(profiler runs)")
     ap.add_argument("--profile-plane", action="store_true",
                     help="only the whole-plane and directional-pass H applies of the plane comparison, 5 "
                          "launches each (profiler runs)")
@@ -354,6 +357,72 @@ def main():
                 res[f"{'x'.join(map(str, n))}_{dt}_x{cnt}"] = row
                 del ph, o
         return res
+
+    def profile_more(iters):
+        """Per-kernel profiles beyond the step's configuration, each launch timed by its own HIP events
+        on the solver's stream: the 3-D 128^3 workload (one instance, FP32 fields and FP64 fields),
+        and the 64-instance sweep's three grid groups (128^2, 256^2, 512^2; each group one batched
+        launch set in FP32, as in the sweep's mixed phase; the largest group's working set is beyond
+        the 256 MB MALL)."""
+        import collections
+        from gpe_inputs import batch_instances, workload_3d
+        out = {}
+        p3, V3, f3 = workload_3d(128)
+        V3d, f3d = torch.from_numpy(V3).to("cuda"), torch.from_numpy(f3).to("cuda")
+        for prec, tag in (("mixed", "fp32"), ("fp64", "fp64")):
+            out[f"3d_128_{tag}"] = kernel_rows(gpe.pcg_profile_batched([p3], [V3d], [f3d], "f64", iters=iters,
+                                                                       precision=prec))
+        groups = collections.defaultdict(list)
+        for bi in batch_instances(64):
+            groups[bi.prob.n[0]].append(bi)
+        for m in sorted(groups):
+            items = groups[m]
+            probs_ = [bi.prob for bi in items]
+            Vs_ = [torch.from_numpy(bi.V).to("cuda") for bi in items]
+            phis_ = [torch.from_numpy(bi.phi0).to("cuda") for bi in items]
+
+            def prof(idx):
+                return gpe.pcg_profile_batched([probs_[k] for k in idx], [Vs_[k] for k in idx],
+                                               [phis_[k] for k in idx], "f64", iters=iters, precision="mixed",
+                                               tol=1e-300)
+
+            # every instance must stay active through the instrumented iterations: a start that ends
+            # within them (its FP32 phase stops at a failed line search) is left out, and counted
+            idx = list(range(len(items)))
+            try:
+                rows = prof(idx)
+            except gpe.GpeError:
+                keep = []
+                for k in idx:
+                    try:
+                        prof([k])
+                        keep.append(k)
+                    except gpe.GpeError:
+                        pass
+                idx = keep
+                try:
+                    rows = prof(idx) if idx else []
+                except gpe.GpeError as exc:
+                    out[f"sweep_{m}x{m}_fp32"] = {"error": str(exc)}
+                    continue
+            out[f"sweep_{m}x{m}_fp32_x{len(idx)}"] = kernel_rows(rows)
+            if len(idx) < len(items):
+                out[f"sweep_{m}x{m}_left_out"] = {"instances": len(items) - len(idx),
+                                                  "reason": "finished within the instrumented iterations"}
+        for rows in out.values():
+            if isinstance(rows, list):
+                for r in rows:
+                    r["frac"] = r["GB_s"] / HBM_PEAK_GBS
+        return out
+
+    if args.profile_more:
+        profile_more(2)  # first launches load the kernels
+        more = profile_more(args.profile_iters)
+        a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)  # counter scale
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_more": True, "copy_bytes": a.numel(), "kernels": more}), flush=True)
+        return
 
     if args.profile_plane:
         rates = plane_rates(profile_run=True)
@@ -682,6 +751,11 @@ def main():
     roofline["frac_of_copy"] = achieved / copy_gbs
     log("[bench] above-MALL profile")
     big = above_mall()
+    log("[bench] 3-D and sweep-group profiles")
+    try:
+        more = profile_more(args.profile_iters)
+    except Exception as exc:  # an extra figure: reported, never fatal to the bench line
+        more = {"error": str(exc)}
     row = next(r for r in big["iteration_fp32_x24"] if r["name"] == name)
     roofline_big = {"bound": "hbm", "achieved": row["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": row["GB_s"] / HBM_PEAK_GBS, "traffic": measured_traffic(f"{name} (fp32 x24)"),
@@ -758,6 +832,7 @@ def main():
                   "E_fp64": [r["E"] for r in reps_fp64], "res_fp64": max(r["res_inf"] for r in reps_fp64)},
         "kernels": {"fp32": kernel_rows(prof32), "fp64": kernel_rows(prof64)},
         "hbm_peak_fractions": hbm_fractions,
+        "kernels_more": more,
         "roofline": roofline,
         "roofline_above_mall": roofline_big,
         "cpu_baseline": cpu,
