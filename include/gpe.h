@@ -169,7 +169,9 @@ typedef struct gpe_pcg_opts {
     int64_t max_iter;
     int32_t precision;     /* 0 = FP64 throughout; 1 = mixed: FP32 fields until the switch, then FP64 */
     int32_t beta_rule;     /* 0 = Polak-Ribiere max(beta_PR, 0); 1 = Fletcher-Reeves */
-    double  switch_res;    /* mixed: leave FP32 once ||r||_inf <= switch_res (or on stagnation) */
+    double  switch_res;    /* mixed: leave FP32 once ||r||_inf <= max(tol_res_inf, switch_res), or on
+                              stagnation: no progress for 100 iterations when tol_res_inf < switch_res
+                              (FP32 cannot finish), else for 400 */
     double  theta_default; /* trial angle when the quadratic model has no minimum */
     int32_t max_halvings;  /* step halvings before the line search gives up */
     int32_t refresh_every; /* recompute L phi from phi every this many iterations (0 = never) */

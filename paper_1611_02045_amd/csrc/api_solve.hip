@@ -26,14 +26,13 @@ using namespace gpe;
 namespace {
 
 // Iterations without progress after which an instance leaves the FP32 phase of a mixed-precision
-// solve (neither ||r||_inf down by 10% nor E down by 1e-9 relative).  Measured on three sets of eight
-// 512^2 starts (Omega = 0.9, beta = 1000) solved to 1e-8, and on the same sets on nested grids
-// 64^2 -> 512^2: against 400, a window of 150 took 4.5% less time in total on the first and 2.5% on
-// the second, and was faster on five of the six sets.  100 took 8.2% less on the first, but there an
-// instance that stops progressing for a little over 100 iterations on a 128^2 level (and later
-// resumes in FP32) was sent to FP64 early and needed 12 900 FP64 iterations, making the nested total
-// 16% longer.
-constexpr int kFp32StallWindow = 150;
+// solve (neither ||r||_inf down by 10% nor E down by 1e-9 relative).  When the tolerance is below
+// switch_res the FP32 phase cannot end the solve and only prepares the FP64 phase: a short window
+// (kFp32WarmupWindow).  When the tolerance is at or above switch_res (coarse nested levels) the FP32
+// phase may meet it alone, and a longer window (kFp32FinishWindow) lets it ride out plateaus of
+// vortex rearrangement instead of handing them to the costlier FP64 phase.
+constexpr int kFp32WarmupWindow = 100;
+constexpr int kFp32FinishWindow = 400;
 
 // Device workspace of one batch of equally sized instances.
 struct BatchWork {
@@ -203,7 +202,7 @@ int solve_batch(BatchWork& w, int B, const gpe_problem_t* probs, bool in_f64, co
                 HIPCHK(convert_real(false, V[b], f32.V + (int64_t)b * N, N, s));
                 hs[b].precision = 1;
                 hs[b].tol_res = std::max(o.tol_res_inf, o.switch_res);
-                hs[b].stall_window = kFp32StallWindow;
+                hs[b].stall_window = o.tol_res_inf < o.switch_res ? kFp32WarmupWindow : kFp32FinishWindow;
             }
             if ((st = run<float>(w, B, f32, hs, o, s)) != GPE_OK) return st;
             HIPCHK(convert_complex(true, f32.phi, f.phi, (int64_t)B * N, s));
